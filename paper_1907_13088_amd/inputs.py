@@ -1,0 +1,387 @@
+"""Seeded synthetic workloads for the finite-element Maxwell field step.
+
+This module only *draws* inputs: initial fields, prescribed current shapes,
+source envelopes and time steps.  It holds none of the solver's arithmetic
+(no discrete curl, no averaging operator, no mass-matrix sweep), so both the
+HIP path and the FP64 oracle can take their inputs from here without sharing
+any of the method's code.
+
+Conventions
+-----------
+* Light speed c = 1; cell sizes default to 1.
+* Arrays are numpy float64, shaped ``(ny, nx)`` in 2D and ``(nz, ny, nx)`` in
+  3D, so that x is the fastest (contiguous) index.
+* Component positions follow the paper's staggered variable list (Sec. 2):
+  E_x at (i+1/2, j, k), E_y at (i, j+1/2, k), E_z at (i, j, k+1/2);
+  B_x at (i, j+1/2, k+1/2), B_y at (i+1/2, j, k+1/2), B_z at (i+1/2, j+1/2, k);
+  J is placed like E.  In 2D the z offsets are dropped.
+* "Courant C" is read as dt = C * dt_CFL, with dt_CFL the Yee-type stability
+  limit the paper derives for this scheme (Sec. 2.1, CFL equations).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+E_OFFSETS = {
+    3: ((0.5, 0.0, 0.0), (0.0, 0.5, 0.0), (0.0, 0.0, 0.5)),
+    2: ((0.5, 0.0), (0.0, 0.5), (0.0, 0.0)),
+}
+B_OFFSETS = {
+    3: ((0.0, 0.5, 0.5), (0.5, 0.0, 0.5), (0.5, 0.5, 0.0)),
+    2: ((0.0, 0.5), (0.5, 0.0), (0.5, 0.5)),
+}
+
+FOUR_PI = 4.0 * math.pi
+
+
+def cfl_dt(d: Sequence[float]) -> float:
+    """Largest stable time step (c = 1): (sum 1/d_i^2)^(-1/2) (Sec. 2.1)."""
+    return 1.0 / math.sqrt(sum(1.0 / (x * x) for x in d))
+
+
+def courant_dt(courant: float, d: Sequence[float]) -> float:
+    return courant * cfl_dt(d)
+
+
+def round_to(dtype, x):
+    """Round a scalar or array to the run dtype, returned as float64."""
+    if np.isscalar(x):
+        return float(np.asarray(x, dtype=dtype))
+    return np.asarray(x, dtype=dtype).astype(np.float64)
+
+
+def _coords(shape: Tuple[int, ...], offset: Sequence[float]):
+    """Per-axis coordinate vectors (x, y[, z]) of a staggered component."""
+    nd = len(shape)
+    out = []
+    for ax in range(nd):  # ax 0 = x
+        n = shape[nd - 1 - ax]
+        out.append(np.arange(n, dtype=np.float64) + offset[ax])
+    return out
+
+
+# --------------------------------------------------------------------------
+# Fourier-mode fields
+# --------------------------------------------------------------------------
+
+@dataclass
+class Mode:
+    n: Tuple[int, ...]   # integer lattice wavevector (n_x, n_y[, n_z])
+    amp: float
+    phase: float
+
+
+def mode_sum(shape: Tuple[int, ...], modes: Sequence[Mode], offset: Sequence[float],
+             weights: Optional[Sequence[float]] = None) -> np.ndarray:
+    """sum_s w_s a_s cos(2 pi n_s . (x + offset) / N + phi_s) on the grid.
+
+    Evaluated with one inverse FFT (all n_s lie on the periodic lattice)."""
+    nd = len(shape)
+    N = shape[::-1]  # (nx, ny[, nz])
+    spec = np.zeros(shape, dtype=np.complex128)
+    for s, md in enumerate(modes):
+        w = 1.0 if weights is None else weights[s]
+        if w == 0.0 or md.amp == 0.0:
+            continue
+        ph = md.phase + 2.0 * math.pi * sum(md.n[a] * offset[a] / N[a] for a in range(nd))
+        idx = tuple(md.n[a] % N[a] for a in reversed(range(nd)))
+        spec[idx] += w * md.amp * complex(math.cos(ph), math.sin(ph))
+    total = 1
+    for x in shape:
+        total *= x
+    return np.real(np.fft.ifftn(spec)) * total
+
+
+def draw_modes(rng: np.random.Generator, N: Sequence[int], count: int, kmax: float) -> List[Mode]:
+    """`count` distinct lattice wavevectors with 0 < |k| <= kmax (k = 2 pi n / N)."""
+    nd = len(N)
+    lim = [int(math.floor(kmax * N[a] / (2 * math.pi))) for a in range(nd)]
+    seen = set()
+    out: List[Mode] = []
+    while len(out) < count:
+        n = tuple(int(rng.integers(-lim[a], lim[a] + 1)) for a in range(nd))
+        k2 = sum((2 * math.pi * n[a] / N[a]) ** 2 for a in range(nd))
+        if k2 == 0.0 or k2 > kmax * kmax or n in seen:
+            continue
+        # a mode and its mirror image would alias onto one real field
+        mirror = tuple(-x for x in n)
+        if mirror in seen:
+            continue
+        seen.add(n)
+        out.append(Mode(n=n, amp=float(rng.normal()), phase=float(rng.uniform(0, 2 * math.pi))))
+    return out
+
+
+def em_wave_fields(shape: Tuple[int, ...], te_modes: Sequence[Mode], tm_modes: Sequence[Mode]):
+    """Continuum-transverse 2D plane waves: TE modes set (E_x, E_y, B_z) with
+    E = a (-k_y, k_x)/|k|, B_z = a; TM modes set (E_z, B_x, B_y) with
+    E_z = a, B = a (k_y, -k_x)/|k|.  Returns (E[3], B[3])."""
+    assert len(shape) == 2
+    ny, nx = shape
+    def unit(md):
+        kx, ky = 2 * math.pi * md.n[0] / nx, 2 * math.pi * md.n[1] / ny
+        kk = math.hypot(kx, ky)
+        return kx / kk, ky / kk
+    te_u = [unit(m) for m in te_modes]
+    tm_u = [unit(m) for m in tm_modes]
+    eo, bo = E_OFFSETS[2], B_OFFSETS[2]
+    E = [mode_sum(shape, te_modes, eo[0], [-u[1] for u in te_u]),
+         mode_sum(shape, te_modes, eo[1], [u[0] for u in te_u]),
+         mode_sum(shape, tm_modes, eo[2])]
+    B = [mode_sum(shape, tm_modes, bo[0], [u[1] for u in tm_u]),
+         mode_sum(shape, tm_modes, bo[1], [-u[0] for u in tm_u]),
+         mode_sum(shape, te_modes, bo[2])]
+    return E, B
+
+
+# --------------------------------------------------------------------------
+# Prescribed currents: Gaussian pulses with a continuum-solenoidal TE part
+# --------------------------------------------------------------------------
+
+@dataclass
+class Pulse:
+    centre: Tuple[float, ...]
+    sigma: float
+    phi: float                     # 2D polarisation angle
+    pol: Tuple[float, float, float] = (0.0, 0.0, 1.0)  # 3D unit vector
+    amp: float = 1.0
+
+
+def _min_image(x: np.ndarray, c: float, n: int) -> np.ndarray:
+    d = x - c
+    return d - n * np.round(d / n)
+
+
+def pulse_current(shape: Tuple[int, ...], pulses: Sequence[Pulse], scale: float = 1.0 / FOUR_PI,
+                  window: float = 6.0):
+    """J0 = sum of pulses (three components, positioned like E).
+
+    2D: psi = cos(phi) sigma g at each point, J_x = d psi/dy, J_y = -d psi/dx
+    (continuum derivatives, so the TE part is solenoidal in the continuum),
+    J_z = sin(phi) g.  3D: J = curl(p sigma g) = grad(sigma g) x p.
+    g = exp(-|x - c|^2 / 2 sigma^2) with periodic minimum image; each pulse is
+    evaluated in a window of +-window*sigma cells."""
+    nd = len(shape)
+    N = shape[::-1]
+    J = [np.zeros(shape) for _ in range(3)]
+    eo = E_OFFSETS[nd]
+    for p in pulses:
+        a = p.amp * scale
+        s = p.sigma
+        h = int(math.ceil(window * s))
+        for comp in range(3):
+            # index windows per axis (periodic)
+            idx, dist = [], []
+            for ax in range(nd):
+                c = p.centre[ax]
+                base = int(math.floor(c - eo[comp][ax]))
+                if 2 * h + 2 < N[ax]:
+                    ii = np.arange(base - h, base + h + 2)
+                else:  # window wider than the grid: every cell once
+                    ii = np.arange(N[ax])
+                x = ii + eo[comp][ax]
+                dist.append(_min_image(x, c, N[ax]))
+                idx.append(np.mod(ii, N[ax]))
+            if nd == 2:
+                dx, dy = np.meshgrid(dist[0], dist[1], indexing="xy")  # (ny, nx)
+                g = np.exp(-(dx * dx + dy * dy) / (2 * s * s))
+                if comp == 0:
+                    val = math.cos(p.phi) * s * g * (-dy / (s * s))
+                elif comp == 1:
+                    val = -math.cos(p.phi) * s * g * (-dx / (s * s))
+                else:
+                    val = math.sin(p.phi) * g
+                np.add.at(J[comp], np.ix_(idx[1], idx[0]), a * val)
+            else:
+                dz, dy, dx = np.meshgrid(dist[2], dist[1], dist[0], indexing="ij")
+                g = np.exp(-(dx * dx + dy * dy + dz * dz) / (2 * s * s))
+                grad = (-dx / s * g, -dy / s * g, -dz / s * g)  # grad(sigma g)
+                px, py, pz = p.pol
+                cross = (grad[1] * pz - grad[2] * py,
+                         grad[2] * px - grad[0] * pz,
+                         grad[0] * py - grad[1] * px)
+                np.add.at(J[comp], np.ix_(idx[2], idx[1], idx[0]), a * cross[comp])
+    return J
+
+
+def draw_pulses(rng: np.random.Generator, N: Sequence[int], count: int, sigma: float = 8.0) -> List[Pulse]:
+    nd = len(N)
+    out = []
+    for _ in range(count):
+        c = tuple(float(rng.uniform(0, N[a])) for a in range(nd))
+        phi = float(rng.uniform(0, 2 * math.pi))
+        v = rng.normal(size=3)
+        v = v / np.linalg.norm(v)
+        out.append(Pulse(centre=c, sigma=sigma, phi=phi, pol=(float(v[0]), float(v[1]), float(v[2]))))
+    return out
+
+
+def envelope(nsteps: int, dt: float, omega: float = 0.3, start: int = 0) -> np.ndarray:
+    """env_n = sin(omega (n + 1/2) dt): the current acts at half steps."""
+    n = np.arange(start, start + nsteps, dtype=np.float64)
+    return np.sin(omega * (n + 0.5) * dt)
+
+
+# --------------------------------------------------------------------------
+# The five workloads
+# --------------------------------------------------------------------------
+
+@dataclass
+class Workload:
+    name: str
+    ndim: int
+    shape: Tuple[int, ...]          # (ny, nx) or (nz, ny, nx)
+    d: Tuple[float, ...]
+    dt: float
+    dtype: str                      # "f32" | "f64"
+    blocks: int                     # bit0 TE, bit1 TM (2D); 3 in 3D
+    sweeps: int                     # m, or m_max when tol > 0
+    tol: float
+    filter_passes: int
+    steps: int
+    E: List[np.ndarray]
+    B: List[np.ndarray]
+    J0: Optional[List[np.ndarray]]
+    env: Optional[np.ndarray]
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def cells(self) -> int:
+        c = 1
+        for x in self.shape:
+            c *= x
+        return c
+
+
+def _finish(w: Workload) -> Workload:
+    """Round every input to the run dtype (both sides see identical values)."""
+    np_dt = np.float32 if w.dtype == "f32" else np.float64
+    w.dt = round_to(np_dt, w.dt)
+    w.E = [round_to(np_dt, a) for a in w.E]
+    w.B = [round_to(np_dt, a) for a in w.B]
+    if w.J0 is not None:
+        w.J0 = [round_to(np_dt, a) for a in w.J0]
+    return w
+
+
+def planewave_te_2d(n: int = 128, courant: float = 0.5, kidx: int = 4, noise: float = 1e-6,
+                    seed: int = 1001, steps: int = 200, tol: float = 1e-12, m_max: int = 200,
+                    dtype: str = "f64") -> Workload:
+    """2D TE plane wave along x (E_y, B_z) plus N(0, noise) on E_x, E_y, B_z."""
+    rng = np.random.default_rng(seed)
+    shape = (n, n)
+    md = [Mode(n=(kidx, 0), amp=1.0, phase=0.0)]
+    E = [np.zeros(shape), mode_sum(shape, md, E_OFFSETS[2][1]), np.zeros(shape)]
+    B = [np.zeros(shape), np.zeros(shape), mode_sum(shape, md, B_OFFSETS[2][2])]
+    for a in (E[0], E[1], B[2]):
+        a += rng.normal(0.0, noise, shape)
+    return _finish(Workload("te_planewave_2d", 2, shape, (1.0, 1.0), courant_dt(courant, (1, 1)), dtype,
+                            1, m_max, tol, 0, steps, E, B, None, None, {"seed": seed, "courant": courant}))
+
+
+def modes_2d(n: Tuple[int, int] = (4096, 4096), courant: float = 0.5, nmodes: int = 256,
+             npulses: int = 64, sigma: float = 8.0, filter_passes: int = 3, m: int = 20,
+             steps: int = 1000, seed: int = 1002, dtype: str = "f32", kmax: float = math.pi / 2,
+             omega: float = 0.3) -> Workload:
+    """2D TE+TM: nmodes random plane waves (|k| <= kmax, N(0,1) amplitudes, TE or
+    TM with probability 1/2) and npulses Gaussian current pulses."""
+    rng = np.random.default_rng(seed)
+    ny, nx = n[1], n[0]
+    shape = (ny, nx)
+    modes = draw_modes(rng, (nx, ny), nmodes, kmax)
+    is_te = rng.uniform(size=nmodes) < 0.5
+    te = [md for md, t in zip(modes, is_te) if t]
+    tm = [md for md, t in zip(modes, is_te) if not t]
+    E, B = em_wave_fields(shape, te, tm)
+    J0 = None
+    env = None
+    dt = courant_dt(courant, (1, 1))
+    if npulses > 0:
+        J0 = pulse_current(shape, draw_pulses(rng, (nx, ny), npulses, sigma))
+        env = envelope(steps, round_to(np.float32 if dtype == "f32" else np.float64, dt), omega)
+    return _finish(Workload("modes_2d", 2, shape, (1.0, 1.0), dt, dtype, 3, m, 0.0,
+                            filter_passes if npulses > 0 else 0, steps, E, B, J0, env,
+                            {"seed": seed, "courant": courant, "nmodes": nmodes, "npulses": npulses}))
+
+
+def planewave_3d(n: int = 512, courant: float = 0.4, kidx: int = 16, noise: float = 1e-3,
+                 npulses: int = 32, sigma: float = 8.0, filter_passes: int = 1, tol: float = 1e-7,
+                 m_max: int = 300, steps: int = 200, seed: int = 1003, dtype: str = "f32",
+                 omega: float = 0.3) -> Workload:
+    """3D plane wave along x (E_y, B_z) plus N(0, noise) on all six components,
+    and npulses solenoidal Gaussian current pulses."""
+    rng = np.random.default_rng(seed)
+    shape = (n, n, n)
+    k = 2 * math.pi * kidx / n
+    x_ey = np.arange(n) + E_OFFSETS[3][1][0]
+    x_bz = np.arange(n) + B_OFFSETS[3][2][0]
+    E = [np.zeros(shape), np.broadcast_to(np.cos(k * x_ey), shape).copy(), np.zeros(shape)]
+    B = [np.zeros(shape), np.zeros(shape), np.broadcast_to(np.cos(k * x_bz), shape).copy()]
+    for a in E + B:
+        a += rng.normal(0.0, noise, shape)
+    dt = courant_dt(courant, (1, 1, 1))
+    J0 = pulse_current(shape, draw_pulses(rng, (n, n, n), npulses, sigma)) if npulses > 0 else None
+    env = envelope(steps, round_to(np.float32 if dtype == "f32" else np.float64, dt), omega) if npulses > 0 else None
+    return _finish(Workload("planewave_3d", 3, shape, (1.0, 1.0, 1.0), dt, dtype, 3, m_max, tol,
+                            filter_passes if npulses > 0 else 0, steps, E, B, J0, env,
+                            {"seed": seed, "courant": courant}))
+
+
+def batch_2d(ngrids: int = 64, sizes: Sequence[int] = (256, 512, 1024, 2048), courant=(0.3, 0.7),
+             nmodes: int = 16, m: int = 20, steps: int = 500, seed: int = 1004, dtype: str = "f32",
+             kmax: float = math.pi / 2) -> List[Workload]:
+    """Independent periodic 2D grids of uneven size and Courant number, no current."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for g in range(ngrids):
+        nx = int(rng.choice(sizes))
+        ny = int(rng.choice(sizes))
+        c = float(rng.uniform(*courant))
+        sub = int(rng.integers(0, 2**31 - 1))
+        w = modes_2d((nx, ny), courant=c, nmodes=nmodes, npulses=0, m=m, steps=steps, seed=sub,
+                     dtype=dtype, kmax=kmax)
+        w.name = f"batch_{g}"
+        w.meta["batch_seed"] = seed
+        out.append(w)
+    return out
+
+
+def adjoint_sources_2d(n: int = 2048, nsrc: int = 256, sigma: float = 8.0, seed: int = 1005,
+                       window: float = 4.0):
+    """Per-source current shapes g_s (the cfg2 polarisation recipe, unit
+    amplitude) stored as local windows: returns (origins[s, 2] as (x0, y0),
+    shapes[s, 3, W, W]) where window cell (a, b) sits at grid cell
+    ((x0 + b) mod n, (y0 + a) mod n), plus amplitudes a_s ~ N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    pulses = draw_pulses(rng, (n, n), nsrc, sigma)
+    amps = rng.normal(size=nsrc)
+    h = int(math.ceil(window * sigma))
+    W = 2 * h + 2
+    origins = np.zeros((nsrc, 2), dtype=np.int64)
+    shapes = np.zeros((nsrc, 3, W, W))
+    for s, p in enumerate(pulses):
+        x0 = int(math.floor(p.centre[0])) - h
+        y0 = int(math.floor(p.centre[1])) - h
+        origins[s] = (x0 % n, y0 % n)
+        # evaluate this pulse on a small periodic patch large enough for the window
+        sub = pulse_current((W, W), [Pulse(centre=(p.centre[0] - x0, p.centre[1] - y0), sigma=sigma,
+                                           phi=p.phi)], window=window)
+        for c in range(3):
+            shapes[s, c] = sub[c]
+    return origins, shapes, amps
+
+
+def assemble_sources(n: int, origins, shapes, amps) -> List[np.ndarray]:
+    """J0 = sum_s a_s g_s on an n x n periodic grid (host-side, float64)."""
+    J = [np.zeros((n, n)) for _ in range(3)]
+    W = shapes.shape[-1]
+    for s in range(shapes.shape[0]):
+        xs = (origins[s, 0] + np.arange(W)) % n
+        ys = (origins[s, 1] + np.arange(W)) % n
+        for c in range(3):
+            np.add.at(J[c], np.ix_(ys, xs), amps[s] * shapes[s, c])
+    return J
