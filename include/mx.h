@@ -1,0 +1,184 @@
+/*
+ * mx.h - C ABI of the MI355X field-step library for the unlumped
+ * finite-element Maxwell solver of Lu et al., "An O(N) Maxwell solver with
+ * improved numerical dispersion properties" (arXiv 1907.13088).
+ *
+ * One time step (Sec. 2.2.1, the update procedure after the A-matrix
+ * equations) maps the state (E^n, B^{n-1/2}) to (E^{n+1}, B^{n+1/2}):
+ *   1. B^{n+1/2} = B^{n-1/2} - c dt curl E^n          (eqs faraday_x..z)
+ *   2. Jf = F^p (env_n J0), p binomial (1,2,1)/4 passes per axis; the
+ *      paper filters the current (Sec. 4.2, Sec. 5) without naming a stencil
+ *   3. dE' = c dt curl(Lambda B^{n+1/2}) - 4 pi dt Jf  (eqs ampere_aux_x..z)
+ *   4. (1 - A) dE = dE' by the fixed-point sweeps of Alg 1,
+ *      A from eqs matrixA_1st..matrixA_last (2D: matrixA_*_2d)
+ *   5. E^{n+1} = E^n + dE
+ * with c = 1, periodic boundaries in every axis.
+ *
+ * Memory model.  The caller owns every byte of device memory: field
+ * buffers are borrowed device pointers and the library's scratch lives in a
+ * caller-provided workspace of mx_workspace_size() bytes.  The library never
+ * allocates device memory.  All kernels run on the HIP stream given to
+ * mx_init (NULL = the default stream).
+ *
+ * Layout.  Each field component is one dense array in the grid dtype
+ * (float or double), x fastest: index (k*ny + j)*nx + i, nz = 1 in 2D.
+ * Components sit at the paper's staggered positions (variable list, Sec. 2):
+ *   Ex (i+1/2, j, k)  Ey (i, j+1/2, k)  Ez (i, j, k+1/2)
+ *   Bx (i, j+1/2, k+1/2)  By (i+1/2, j, k+1/2)  Bz (i+1/2, j+1/2, k)
+ *   J like E.  E is at time level n, B at n - 1/2 (B first, then E).
+ *
+ * Errors.  Every call returns MX_OK (0) or a negative code; the message of
+ * the calling thread's last failure is given by mx_last_error().  Argument
+ * errors are detected on the host before any device work.  Non-convergence
+ * of a tolerance solve is not an error: it is flagged in mx_step_stats.
+ */
+#ifndef MX_H
+#define MX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MX_OK            0
+#define MX_EINVAL       -1   /* bad argument: NULL, size, enum, layout */
+#define MX_ECFL         -2   /* dt above the stability limit (Sec. 2.1) */
+#define MX_EWORKSPACE   -3   /* workspace missing or smaller than required */
+#define MX_EDEVICE      -4   /* HIP runtime error */
+#define MX_ENONFINITE   -5   /* a residual norm became NaN or Inf */
+#define MX_ESTATE       -6   /* call out of order (e.g. step before bind) */
+
+#define MX_F32 0
+#define MX_F64 1
+
+/* decoupled blocks: in 2D TE = (Ex, Ey, Bz) and TM = (Ez, Bx, By) evolve
+   independently (Sec. 2.2.2); 3D always uses MX_ALL */
+#define MX_TE  1
+#define MX_TM  2
+#define MX_ALL 3
+
+/* iterate form of the tolerance solve (a reading, not in the paper):
+   STANDARD keeps x_(j+1) = dE' + A x_(j) (Alg 1); DELTA keeps
+   d_(j+1) = A d_(j) and s_(j+1) = s_(j) + d_(j+1), identical in exact
+   arithmetic, whose step norm |d| has no FP32 rounding floor */
+#define MX_FORM_STANDARD 0
+#define MX_FORM_DELTA    1
+
+/* init-time warnings (bit flags) */
+#define MX_WARN_NOCONV_GUARANTEE 1  /* 3D, dt > min(d)/sqrt(2): the infinity-norm
+                                       convergence bound of Appendix C does not hold */
+
+typedef struct mx_config {
+    int ndim;             /* 2 or 3 */
+    int64_t n[3];         /* cells per axis; n[2] ignored (1) in 2D */
+    double d[3];          /* cell sizes dx, dy, dz (> 0) */
+    double dt;            /* time step, c = 1; must satisfy the CFL bound */
+    int dtype;            /* MX_F32 or MX_F64 */
+    int blocks;           /* 2D: MX_TE, MX_TM or MX_ALL; 3D: MX_ALL */
+    int sweeps;           /* m when tol == 0; m_max when tol > 0 (>= 0) */
+    double tol;           /* 0: fixed m (the paper's choice, Sec. 2.2.1);
+                             > 0: stop when ||dE_(j+1) - dE_(j)||_2 <= tol ||dE'||_2
+                             per block, tested after every pass of sweeps */
+    int filter_passes;    /* p >= 0 */
+    int lumped;           /* 1: averaging operators lumped, the Yee scheme (Sec. 2) */
+    double four_pi;       /* source constant, 4 pi in Gaussian units */
+    int form;             /* MX_FORM_STANDARD or MX_FORM_DELTA */
+    int sweeps_per_pass;  /* sweeps fused per pass over HBM; 0 = library choice */
+} mx_config;
+
+typedef struct mx_step_stats {
+    int sweeps[2];        /* sweeps taken per block (2D: TE, TM; 3D: [0]) */
+    double resid[2];      /* last step norm ||dE_(j+1) - dE_(j)||_2 (tol mode) */
+    double rhs[2];        /* ||dE'||_2 (tol mode) */
+    int nonconverged[2];  /* tol mode: m_max reached above tolerance */
+} mx_step_stats;
+
+typedef struct mx_grid mx_grid;
+
+/* Thread-local message of the last failed call ("" if none). */
+const char *mx_last_error(void);
+
+/* Fill *cfg with defaults: 2D, unit cells, FP32, MX_ALL, m = 20, tol = 0,
+   no filter, 4 pi, standard form.  n and dt must still be set. */
+int mx_config_default(mx_config *cfg);
+
+/* Host-only validation (no device call): ranges, enums and the CFL bound
+   dt <= (sum_i 1/d_i^2)^(-1/2) (Sec. 2.1).  *warn receives MX_WARN_* bits
+   (may be NULL). */
+int mx_validate(const mx_config *cfg, int *warn);
+
+/* Bytes of device workspace mx_init needs for cfg (host-only). */
+int mx_workspace_size(const mx_config *cfg, size_t *bytes);
+
+/* Create a grid.  `stream` is a hipStream_t (NULL = default stream);
+   `workspace` a device buffer of at least mx_workspace_size() bytes, owned
+   by the caller and kept alive until mx_destroy.  Validates like
+   mx_validate.  Sets the current device to the one `workspace` is on. */
+int mx_init(const mx_config *cfg, void *stream, void *workspace, size_t workspace_bytes,
+            mx_grid **out);
+
+/* Bind the state: E[3] at level n and B[3] at level n - 1/2, borrowed
+   device pointers in the grid dtype and layout (updated in place). */
+int mx_bind_fields(mx_grid *g, void *const E[3], void *const B[3]);
+
+/* Bind the prescribed current shape J0[3] (device pointers, layout of E,
+   borrowed, read only); J0 == NULL removes the source. */
+int mx_set_current(mx_grid *g, void *const J0[3]);
+
+/* Advance nsteps steps.  env (host, nsteps doubles, may be NULL = 0)
+   scales J0 at step s, i.e. at t = (n + s + 1/2) dt.  replay (host,
+   2*nsteps ints, may be NULL) forces the per-block sweep counts of each
+   step instead of the configured rule.  stats (host, nsteps entries, may
+   be NULL) receives per-step counts and norms.  Asynchronous on the stream
+   unless tol > 0 (then it waits for each residual check). */
+int mx_step(mx_grid *g, int nsteps, const double *env, const int *replay, mx_step_stats *stats);
+
+/* Step counter n of the bound state. */
+int mx_get_step(mx_grid *g, int64_t *n);
+int mx_set_step(mx_grid *g, int64_t n);
+
+/* Sweeps fused per HBM pass in use (the library's or the configured choice). */
+int mx_get_sweeps_per_pass(mx_grid *g, int *k);
+
+int mx_destroy(mx_grid *g);
+
+/* ------------------------------------------------------------------------
+ * Transposed (adjoint) step.  The step is linear in (E, B, J0):
+ *   B+ = B - dt K E,   E+ = E + P (dt K^T Lambda B+ - 4 pi dt env F J0),
+ * K the E->B curl of eqs faraday_*, K^T the B->E curl of eqs ampere_aux_*,
+ * Lambda = diag(alpha_x, alpha_y, alpha_z), P = sum_{j<=m} A^j (Alg 1) and
+ * F the filter.  A is symmetric (Appendix C), as are Lambda and F, so the
+ * transposed step is
+ *   v = P Ebar;  Bbar += dt Lambda K v;  Ebar -= dt K^T Bbar;
+ *   dJ0 += env (-4 pi dt) F v.
+ * mx_adjoint runs nsteps transposed steps in reverse order for forward steps
+ * n0 .. n0+nsteps-1: env[s] and sweeps[2s], sweeps[2s+1] are those of
+ * forward step n0+s.  Ebar, Bbar (device, grid layout, in: gradient with
+ * respect to the state after the steps, out: before) are updated in place;
+ * dJ0 (device, may be NULL) accumulates the gradient with respect to J0.
+ * Uses the grid's workspace; the bound fields are not touched.
+ * ------------------------------------------------------------------------ */
+int mx_adjoint(mx_grid *g, int nsteps, const double *env, const int *sweeps,
+               void *const Ebar[3], void *const Bbar[3], void *const dJ0[3]);
+
+/* ------------------------------------------------------------------------
+ * Localised 2D source shapes.  Source s has three W x W windows
+ * shapes[((s*3 + c)*W + a)*W + b] (device, grid dtype) whose cell (a, b)
+ * lands on grid cell ((x0_s + b) mod nx, (y0_s + a) mod ny), with
+ * origins[2s] = x0_s, origins[2s+1] = y0_s (device int64).
+ *   mx_sources_assemble:  J0 = sum_s amps[s] shape_s   (J0 overwritten)
+ *   mx_sources_project:   grad[s] = <shape_s, G>        (the transpose)
+ * amps and grad are device arrays of nsrc values in the grid dtype.
+ * ------------------------------------------------------------------------ */
+int mx_sources_assemble(mx_grid *g, int nsrc, int W, const int64_t *origins, const void *shapes,
+                        const void *amps, void *const J0[3]);
+int mx_sources_project(mx_grid *g, int nsrc, int W, const int64_t *origins, const void *shapes,
+                       void *const G[3], void *grad);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MX_H */

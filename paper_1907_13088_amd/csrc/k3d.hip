@@ -1,0 +1,305 @@
+// 3D kernels of the field step (arXiv 1907.13088, Sec. 2.2.1):
+//   Faraday update ........ eqs faraday_x..z
+//   current filter ........ p passes of (1,2,1)/4 along x, y and z
+//   auxiliary increment ... eqs ampere_aux_x..z
+//   mass-matrix sweep ..... Alg 1 with A from eqs matrixA_1st..matrixA_last
+// One thread per cell, 64 x 4 threads per workgroup along x and y, one z
+// plane per workgroup row of the grid; neighbour values come through the
+// vector caches.
+#include "mx_internal.h"
+
+namespace mx {
+namespace {
+
+constexpr int NT = 256;
+constexpr int BXT = 64, BYT = 4;
+
+__device__ __forceinline__ int wrap1(int i, int n)
+{
+    // i is within one period of [0, n)
+    return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
+struct Idx3 {
+    int nx, ny, nz;
+    int i, j, k;
+    __device__ __forceinline__ size_t at(int di, int dj, int dk) const
+    {
+        const int x = wrap1(i + di, nx), y = wrap1(j + dj, ny), z = wrap1(k + dk, nz);
+        return ((size_t)z * ny + y) * nx + x;
+    }
+};
+
+__device__ void block_sum2(double &a, double &b, double *sh)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) { sh[2 * w] = a; sh[2 * w + 1] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = 0.0; b = 0.0;
+        for (int q = 0; q < NT / 64; q++) { a += sh[2 * q]; b += sh[2 * q + 1]; }
+    }
+}
+
+__device__ __forceinline__ bool cell(int nx, int ny, Idx3 &id)
+{
+    const int tx = threadIdx.x & (BXT - 1), ty = threadIdx.x / BXT;
+    id.i = blockIdx.x * BXT + tx;
+    id.j = blockIdx.y * BYT + ty;
+    id.k = blockIdx.z;
+    return id.i < nx && id.j < ny;
+}
+
+// alpha along an axis in "1 + small" form: f + (f- + f+ - 2 f)/6
+template <typename T>
+__device__ __forceinline__ T avg(T fm, T f0, T fp, int lumped)
+{
+    return lumped ? f0 : f0 + (fm + fp - T(2) * f0) * T(1.0 / 6.0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k3_filter_axis(Coef<T> c, int axis, const T *src, T *dst)
+{
+    Idx3 id{c.nx, c.ny, c.nz, 0, 0, 0};
+    if (!cell(c.nx, c.ny, id)) return;
+    const int di = axis == 0, dj = axis == 1, dk = axis == 2;
+    dst[id.at(0, 0, 0)] = T(0.25) * src[id.at(-di, -dj, -dk)] + T(0.5) * src[id.at(0, 0, 0)]
+                        + T(0.25) * src[id.at(di, dj, dk)];
+}
+
+// B^{n+1/2} = B^{n-1/2} - dt curl E^n, in place (reads only E neighbours)
+template <typename T>
+__global__ __launch_bounds__(NT) void k3_faraday(Coef<T> c, const T *Ex, const T *Ey, const T *Ez,
+                                                 T *Bx, T *By, T *Bz)
+{
+    Idx3 id{c.nx, c.ny, c.nz, 0, 0, 0};
+    if (!cell(c.nx, c.ny, id)) return;
+    const size_t o = id.at(0, 0, 0);
+    const T ex = Ex[o], ey = Ey[o], ez = Ez[o];
+    Bx[o] -= c.tdy * (Ez[id.at(0, 1, 0)] - ez) - c.tdz * (Ey[id.at(0, 0, 1)] - ey);
+    By[o] -= c.tdz * (Ex[id.at(0, 0, 1)] - ex) - c.tdx * (Ez[id.at(1, 0, 0)] - ez);
+    Bz[o] -= c.tdx * (Ey[id.at(1, 0, 0)] - ey) - c.tdy * (Ex[id.at(0, 1, 0)] - ex);
+}
+
+// dE' = dt curl(Lambda B^{n+1/2}) - 4 pi dt env Jf
+template <typename T>
+__global__ __launch_bounds__(NT) void k3_rhs(Coef<T> c, const T *Bx, const T *By, const T *Bz,
+                                             const T *Jx, const T *Jy, const T *Jz, T env_src,
+                                             T *dx_, T *dy_, T *dz_, double *partial)
+{
+    __shared__ double sred[2 * NT / 64];
+    Idx3 id{c.nx, c.ny, c.nz, 0, 0, 0};
+    const bool ok = cell(c.nx, c.ny, id);
+    double acc = 0.0, dummy = 0.0;
+    if (ok) {
+        const int L = c.lumped;
+        // alpha_z Bz at (i, j) and (i, j-1), (i-1, j)
+        auto azBz = [&](int di, int dj) {
+            return avg(Bz[id.at(di, dj, -1)], Bz[id.at(di, dj, 0)], Bz[id.at(di, dj, 1)], L);
+        };
+        // alpha_y By at (i, k), (i-1, k), (i, k-1)
+        auto ayBy = [&](int di, int dk) {
+            return avg(By[id.at(di, -1, dk)], By[id.at(di, 0, dk)], By[id.at(di, 1, dk)], L);
+        };
+        // alpha_x Bx at (j, k), (j-1, k), (j, k-1)
+        auto axBx = [&](int dj, int dk) {
+            return avg(Bx[id.at(-1, dj, dk)], Bx[id.at(0, dj, dk)], Bx[id.at(1, dj, dk)], L);
+        };
+        const T azbz = azBz(0, 0), ayby = ayBy(0, 0), axbx = axBx(0, 0);
+        const T cx = c.tdy * (azbz - azBz(0, -1)) - c.tdz * (ayby - ayBy(0, -1));
+        const T cy = c.tdz * (axbx - axBx(0, -1)) - c.tdx * (azbz - azBz(-1, 0));
+        const T cz = c.tdx * (ayby - ayBy(-1, 0)) - c.tdy * (axbx - axBx(-1, 0));
+        const size_t o = id.at(0, 0, 0);
+        const T vx = cx - (Jx ? env_src * Jx[o] : T(0));
+        const T vy = cy - (Jy ? env_src * Jy[o] : T(0));
+        const T vz = cz - (Jz ? env_src * Jz[o] : T(0));
+        dx_[o] = vx; dy_[o] = vy; dz_[o] = vz;
+        acc = (double)vx * vx + (double)vy * vy + (double)vz * vz;
+    }
+    if (partial != nullptr) {
+        block_sum2(acc, dummy, sred);
+        if (threadIdx.x == 0) {
+            const size_t wg = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+            partial[2 * wg] = acc;
+            partial[2 * wg + 1] = 0.0;
+        }
+    }
+}
+
+// (A x)_component at the cell, 33-point stencil per component
+template <typename T>
+__device__ __forceinline__ void apply_A3(const Coef<T> &c, const Idx3 &id, const T *X, const T *Y,
+                                         const T *Z, T &ax, T &ay, T &az)
+{
+    const int L = 0;
+    auto d2 = [&](const T *F, int di, int dj, int dk, int ei, int ej, int ek) {
+        // second difference of F along axis e at offset d
+        return F[id.at(di + ei, dj + ej, dk + ek)] + F[id.at(di - ei, dj - ej, dk - ek)]
+               - T(2) * F[id.at(di, dj, dk)];
+    };
+    // --- x component: A_xx X + A_xy Y + A_xz Z
+    {
+        const T dyy = d2(X, 0, 0, 0, 0, 1, 0);
+        const T dzz = d2(X, 0, 0, 0, 0, 0, 1);
+        const T dyyzz = d2(X, 0, 1, 0, 0, 0, 1) + d2(X, 0, -1, 0, 0, 0, 1) - T(2) * dzz;
+        // Dbar_x Dbar_y Y at (i+1/2, j, k+dk): Y at (i, j+1/2, k)
+        auto dxdyY = [&](int dk) {
+            return (Y[id.at(1, 0, dk)] - Y[id.at(1, -1, dk)]) - (Y[id.at(0, 0, dk)] - Y[id.at(0, -1, dk)]);
+        };
+        auto dxdzZ = [&](int dj) {
+            return (Z[id.at(1, dj, 0)] - Z[id.at(1, dj, -1)]) - (Z[id.at(0, dj, 0)] - Z[id.at(0, dj, -1)]);
+        };
+        ax = c.a3[0][0] * dyy + c.a3[0][1] * dzz + c.a3[0][2] * dyyzz
+           + c.o3[2] * avg(dxdyY(-1), dxdyY(0), dxdyY(1), L)
+           + c.o3[1] * avg(dxdzZ(-1), dxdzZ(0), dxdzZ(1), L);
+    }
+    // --- y component: A_yy Y + A_yx X + A_yz Z
+    {
+        const T dzz = d2(Y, 0, 0, 0, 0, 0, 1);
+        const T dxx = d2(Y, 0, 0, 0, 1, 0, 0);
+        const T dzzxx = d2(Y, 1, 0, 0, 0, 0, 1) + d2(Y, -1, 0, 0, 0, 0, 1) - T(2) * dzz;
+        auto dydxX = [&](int dk) {
+            return (X[id.at(0, 1, dk)] - X[id.at(-1, 1, dk)]) - (X[id.at(0, 0, dk)] - X[id.at(-1, 0, dk)]);
+        };
+        auto dydzZ = [&](int di) {
+            return (Z[id.at(di, 1, 0)] - Z[id.at(di, 1, -1)]) - (Z[id.at(di, 0, 0)] - Z[id.at(di, 0, -1)]);
+        };
+        ay = c.a3[1][0] * dzz + c.a3[1][1] * dxx + c.a3[1][2] * dzzxx
+           + c.o3[2] * avg(dydxX(-1), dydxX(0), dydxX(1), L)
+           + c.o3[0] * avg(dydzZ(-1), dydzZ(0), dydzZ(1), L);
+    }
+    // --- z component: A_zz Z + A_zx X + A_zy Y
+    {
+        const T dxx = d2(Z, 0, 0, 0, 1, 0, 0);
+        const T dyy = d2(Z, 0, 0, 0, 0, 1, 0);
+        const T dxxyy = d2(Z, 0, 1, 0, 1, 0, 0) + d2(Z, 0, -1, 0, 1, 0, 0) - T(2) * dxx;
+        auto dzdxX = [&](int dj) {
+            return (X[id.at(0, dj, 1)] - X[id.at(-1, dj, 1)]) - (X[id.at(0, dj, 0)] - X[id.at(-1, dj, 0)]);
+        };
+        auto dzdyY = [&](int di) {
+            return (Y[id.at(di, 0, 1)] - Y[id.at(di, -1, 1)]) - (Y[id.at(di, 0, 0)] - Y[id.at(di, -1, 0)]);
+        };
+        az = c.a3[2][0] * dxx + c.a3[2][1] * dyy + c.a3[2][2] * dxxyy
+           + c.o3[1] * avg(dzdxX(-1), dzdxX(0), dzdxX(1), L)
+           + c.o3[0] * avg(dzdyY(-1), dzdyY(0), dzdyY(1), L);
+    }
+}
+
+template <typename T, bool DELTA>
+__global__ __launch_bounds__(NT) void k3_sweep(Coef<T> c, SweepArgs<T> a, int flags)
+{
+    __shared__ double sred[2 * NT / 64];
+    Idx3 id{c.nx, c.ny, c.nz, 0, 0, 0};
+    const bool ok = cell(c.nx, c.ny, id);
+    double acc = 0.0, dummy = 0.0;
+    if (ok) {
+        const bool first = flags & SW_FIRST;
+        const T *X = first ? a.rhs[0] : a.x_in[0];
+        const T *Y = first ? a.rhs[1] : a.x_in[1];
+        const T *Z = first ? a.rhs[2] : a.x_in[2];
+        T ax, ay, az;
+        apply_A3(c, id, X, Y, Z, ax, ay, az);
+        const size_t o = id.at(0, 0, 0);
+        T v[3];
+        if (!DELTA) {
+            v[0] = a.rhs[0][o] + ax; v[1] = a.rhs[1][o] + ay; v[2] = a.rhs[2][o] + az;
+        } else {
+            v[0] = ax; v[1] = ay; v[2] = az;
+        }
+        const T *xin[3] = {X, Y, Z};
+        for (int q = 0; q < 3; q++) {
+            if (flags & SW_RESID) {
+                const double d = DELTA ? (double)v[q] : (double)v[q] - (double)xin[q][o];
+                acc += d * d;
+            }
+            T sum = T(0);
+            if (DELTA) sum = (first ? a.rhs[q][o] : a.s_in[q][o]) + v[q];
+            if (flags & SW_STORE) {
+                a.x_out[q][o] = v[q];
+                if (DELTA) a.s_out[q][o] = sum;
+            }
+            if (flags & SW_LAST) a.E[q][o] += DELTA ? sum : v[q];
+        }
+    }
+    if (flags & SW_RESID) {
+        block_sum2(acc, dummy, sred);
+        if (threadIdx.x == 0) {
+            const size_t wg = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+            a.partial[2 * wg] = acc;
+            a.partial[2 * wg + 1] = 0.0;
+        }
+    }
+}
+
+dim3 grid3(int nx, int ny, int nz) { return dim3((nx + BXT - 1) / BXT, (ny + BYT - 1) / BYT, nz); }
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_filter3d(const Coef<T> &c, int passes, const T *const J0[3], T *const Jf[3],
+                           T *const tmp[3], hipStream_t s)
+{
+    // 3 * passes axis sweeps per component, ping-ponging so the last lands in Jf
+    const int total = 3 * passes;
+    for (int q = 0; q < 3; q++) {
+        if (total == 0) {
+            hipMemcpyAsync(Jf[q], J0[q], sizeof(T) * (size_t)c.nx * c.ny * c.nz, hipMemcpyDeviceToDevice, s);
+            continue;
+        }
+        const T *src = J0[q];
+        for (int t = 0; t < total; t++) {
+            T *dst = ((total - 1 - t) % 2 == 0) ? Jf[q] : tmp[q];
+            hipLaunchKernelGGL((k3_filter_axis<T>), grid3(c.nx, c.ny, c.nz), dim3(NT), 0, s, c, t % 3, src, dst);
+            src = dst;
+        }
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_faraday3d(const Coef<T> &c, const T *const E[3], T *const B[3], hipStream_t s)
+{
+    hipLaunchKernelGGL((k3_faraday<T>), grid3(c.nx, c.ny, c.nz), dim3(NT), 0, s, c, E[0], E[1], E[2],
+                       B[0], B[1], B[2]);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rhs3d(const Coef<T> &c, const T *const B[3], const T *const Jf[3], T env_src,
+                        T *const dEp[3], double *partial, hipStream_t s, int *nwg)
+{
+    dim3 g = grid3(c.nx, c.ny, c.nz);
+    *nwg = g.x * g.y * g.z;
+    hipLaunchKernelGGL((k3_rhs<T>), g, dim3(NT), 0, s, c, B[0], B[1], B[2], Jf ? Jf[0] : nullptr,
+                       Jf ? Jf[1] : nullptr, Jf ? Jf[2] : nullptr, env_src, dEp[0], dEp[1], dEp[2], partial);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sweep3d(const Coef<T> &c, bool delta, int flags, const SweepArgs<T> &a,
+                          hipStream_t s, int *nwg)
+{
+    dim3 g = grid3(c.nx, c.ny, c.nz);
+    *nwg = g.x * g.y * g.z;
+    if (delta) hipLaunchKernelGGL((k3_sweep<T, true>), g, dim3(NT), 0, s, c, a, flags);
+    else hipLaunchKernelGGL((k3_sweep<T, false>), g, dim3(NT), 0, s, c, a, flags);
+    return hipGetLastError();
+}
+
+#define INST(T)                                                                                       \
+    template hipError_t launch_filter3d<T>(const Coef<T> &, int, const T *const[3], T *const[3],      \
+                                           T *const[3], hipStream_t);                                 \
+    template hipError_t launch_faraday3d<T>(const Coef<T> &, const T *const[3], T *const[3], hipStream_t); \
+    template hipError_t launch_rhs3d<T>(const Coef<T> &, const T *const[3], const T *const[3], T,     \
+                                        T *const[3], double *, hipStream_t, int *);                   \
+    template hipError_t launch_sweep3d<T>(const Coef<T> &, bool, int, const SweepArgs<T> &, hipStream_t, int *);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace mx

@@ -1,0 +1,575 @@
+// Host side of the C ABI declared in include/mx.h: validation, workspace
+// layout, the per-step launch schedule (front pass, sweep passes, residual
+// checks, E increment) and the transposed step.
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mx_internal.h"
+
+using namespace mx;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return fail(MX_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+int64_t ncell_of(const mx_config *c) { return c->n[0] * c->n[1] * (c->ndim == 3 ? c->n[2] : 1); }
+size_t elem_of(const mx_config *c) { return c->dtype == MX_F64 ? 8 : 4; }
+
+// upper bound on workgroups of any launch that writes partial sums
+int64_t max_wg(const mx_config *c)
+{
+    const int64_t nx = c->n[0], ny = c->n[1], nz = c->ndim == 3 ? c->n[2] : 1;
+    // 2D front tiles 64x16, 2D sweep tiles 64x8 at the smallest, 3D 64x4 per plane
+    const int64_t a = ((nx + 63) / 64) * ((ny + 3) / 4) * nz;
+    return a;
+}
+
+int default_spp(const mx_config *c)
+{
+    if (c->ndim == 3) return 1;
+    return c->dtype == MX_F64 ? 4 : 5;
+}
+
+// number of full-grid arrays in the workspace
+int n_arrays(const mx_config *c)
+{
+    // dE' (3), two iterate buffers (6), running sum (3), then
+    // 2D: a second B buffer (3); 3D: filtered current and a filter temp (6)
+    return c->ndim == 2 ? 15 : 18;
+}
+
+}  // namespace
+
+struct mx_grid {
+    mx_config cfg;
+    hipStream_t stream;
+    int device;
+    char *ws;
+    size_t ws_bytes;
+    int64_t ncell;
+    int64_t step;
+    void *E[3], *B[3], *J0[3];
+    bool bound, has_j;
+    void *dEp[3], *X[2][3], *S[3], *Bws[3], *Jf[3], *Jt[3];
+    int bloc[3];          // 2D: where component q of B currently lives (0 user, 1 workspace)
+    double *partial;      // device
+    double *red;          // device, 2 doubles
+    int spp;
+    Coef<float> cf;
+    Coef<double> cd;
+};
+
+template <typename T>
+static void fill_coef(const mx_config *c, Coef<T> &k)
+{
+    const double dt = c->dt;
+    const double dx = c->d[0], dy = c->d[1], dz = c->ndim == 3 ? c->d[2] : 1.0;
+    const double rx = dt * dt / (dx * dx), ry = dt * dt / (dy * dy), rz = dt * dt / (dz * dz);
+    const double rxy = dt * dt / (dx * dy), ryz = dt * dt / (dy * dz), rzx = dt * dt / (dz * dx);
+    k.nx = (int)c->n[0];
+    k.ny = (int)c->n[1];
+    k.nz = c->ndim == 3 ? (int)c->n[2] : 1;
+    k.tdx = (T)(dt / dx);
+    k.tdy = (T)(dt / dy);
+    k.tdz = (T)(dt / dz);
+    k.src = (T)(c->four_pi * dt);
+    k.cxx = (T)((ry - 1.0) / 6.0);
+    k.cyy = (T)((rx - 1.0) / 6.0);
+    k.cxy = (T)(-rxy / 6.0);
+    k.czx = (T)((rx - 1.0) / 6.0);
+    k.czy = (T)((ry - 1.0) / 6.0);
+    k.czz = (T)((rx + ry - 1.0) / 36.0);
+    const double r[3] = {rx, ry, rz};
+    for (int i = 0; i < 3; i++) {
+        const int j = (i + 1) % 3, l = (i + 2) % 3;
+        k.a3[i][0] = (T)((r[j] - 1.0) / 6.0);
+        k.a3[i][1] = (T)((r[l] - 1.0) / 6.0);
+        k.a3[i][2] = (T)((r[j] + r[l] - 1.0) / 36.0);
+    }
+    k.o3[0] = (T)(-ryz / 6.0);
+    k.o3[1] = (T)(-rzx / 6.0);
+    k.o3[2] = (T)(-rxy / 6.0);
+    k.lumped = c->lumped;
+}
+
+extern "C" {
+
+const char *mx_last_error(void) { return g_err.c_str(); }
+
+int mx_config_default(mx_config *cfg)
+{
+    if (!cfg) return fail(MX_EINVAL, "cfg is NULL");
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->ndim = 2;
+    cfg->n[0] = cfg->n[1] = cfg->n[2] = 1;
+    cfg->d[0] = cfg->d[1] = cfg->d[2] = 1.0;
+    cfg->dtype = MX_F32;
+    cfg->blocks = MX_ALL;
+    cfg->sweeps = 20;
+    cfg->four_pi = 4.0 * M_PI;
+    cfg->form = MX_FORM_STANDARD;
+    return MX_OK;
+}
+
+int mx_validate(const mx_config *c, int *warn)
+{
+    if (warn) *warn = 0;
+    if (!c) return fail(MX_EINVAL, "cfg is NULL");
+    if (c->ndim != 2 && c->ndim != 3) return fail(MX_EINVAL, "ndim must be 2 or 3 (got %d)", c->ndim);
+    for (int a = 0; a < c->ndim; a++) {
+        if (c->n[a] < 1 || c->n[a] > (1LL << 30))
+            return fail(MX_EINVAL, "n[%d] = %lld out of range [1, 2^30]", a, (long long)c->n[a]);
+        if (!(c->d[a] > 0.0) || !std::isfinite(c->d[a]))
+            return fail(MX_EINVAL, "d[%d] must be positive and finite", a);
+    }
+    if (ncell_of(c) > (1LL << 40)) return fail(MX_EINVAL, "too many cells");
+    if (c->dtype != MX_F32 && c->dtype != MX_F64) return fail(MX_EINVAL, "dtype must be MX_F32 or MX_F64");
+    if (c->ndim == 2 && (c->blocks < 1 || c->blocks > 3)) return fail(MX_EINVAL, "blocks must be MX_TE, MX_TM or MX_ALL");
+    if (c->ndim == 3 && c->blocks != MX_ALL) return fail(MX_EINVAL, "3D grids step all components (MX_ALL)");
+    if (c->sweeps < 0 || c->sweeps > 1000000) return fail(MX_EINVAL, "sweeps out of range");
+    if (!(c->tol >= 0.0) || !std::isfinite(c->tol)) return fail(MX_EINVAL, "tol must be finite and >= 0");
+    if (c->filter_passes < 0 || c->filter_passes > 4) return fail(MX_EINVAL, "filter_passes must be in [0, 4]");
+    if (c->lumped != 0 && c->lumped != 1) return fail(MX_EINVAL, "lumped must be 0 or 1");
+    if (!std::isfinite(c->four_pi)) return fail(MX_EINVAL, "four_pi must be finite");
+    if (c->form != MX_FORM_STANDARD && c->form != MX_FORM_DELTA) return fail(MX_EINVAL, "bad form");
+    if (c->sweeps_per_pass < 0 || c->sweeps_per_pass > 8) return fail(MX_EINVAL, "sweeps_per_pass must be in [0, 8]");
+    if (c->ndim == 3 && c->sweeps_per_pass > 1) return fail(MX_EINVAL, "3D grids run one sweep per pass");
+    if (!(c->dt > 0.0) || !std::isfinite(c->dt)) return fail(MX_EINVAL, "dt must be positive and finite");
+    double s = 0.0;
+    for (int a = 0; a < c->ndim; a++) s += 1.0 / (c->d[a] * c->d[a]);
+    const double dt_cfl = 1.0 / std::sqrt(s);
+    if (c->dt > dt_cfl * (1.0 + 1e-12))
+        return fail(MX_ECFL, "dt = %.17g exceeds the stability limit %.17g", c->dt, dt_cfl);
+    if (c->ndim == 3) {
+        const double dmin = std::min(c->d[0], std::min(c->d[1], c->d[2]));
+        if (c->dt > dmin / std::sqrt(2.0) && warn) *warn |= MX_WARN_NOCONV_GUARANTEE;
+    }
+    return MX_OK;
+}
+
+int mx_workspace_size(const mx_config *c, size_t *bytes)
+{
+    int rc = mx_validate(c, nullptr);
+    if (rc) return rc;
+    if (!bytes) return fail(MX_EINVAL, "bytes is NULL");
+    const size_t arr = up((size_t)ncell_of(c) * elem_of(c));
+    *bytes = n_arrays(c) * arr + up((size_t)max_wg(c) * 2 * sizeof(double)) + up(8 * sizeof(double));
+    return MX_OK;
+}
+
+int mx_init(const mx_config *cfg, void *stream, void *workspace, size_t workspace_bytes, mx_grid **out)
+{
+    if (!out) return fail(MX_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = mx_validate(cfg, nullptr);
+    if (rc) return rc;
+    size_t need = 0;
+    mx_workspace_size(cfg, &need);
+    if (!workspace) return fail(MX_EWORKSPACE, "workspace is NULL (%zu bytes needed)", need);
+    if (workspace_bytes < need)
+        return fail(MX_EWORKSPACE, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, need);
+    if (((uintptr_t)workspace) % ALIGN) return fail(MX_EINVAL, "workspace must be %zu-byte aligned", ALIGN);
+    hipPointerAttribute_t attr;
+    HIPCHK(hipPointerGetAttributes(&attr, workspace));
+    if (attr.type != hipMemoryTypeDevice) return fail(MX_EINVAL, "workspace is not device memory");
+    HIPCHK(hipSetDevice(attr.device));
+
+    mx_grid *g = new mx_grid();
+    g->cfg = *cfg;
+    g->stream = (hipStream_t)stream;
+    g->device = attr.device;
+    g->ws = (char *)workspace;
+    g->ws_bytes = workspace_bytes;
+    g->ncell = ncell_of(cfg);
+    g->step = 0;
+    g->bound = false;
+    g->has_j = false;
+    g->spp = cfg->sweeps_per_pass > 0 ? cfg->sweeps_per_pass : default_spp(cfg);
+    const size_t arr = up((size_t)g->ncell * elem_of(cfg));
+    char *p = g->ws;
+    auto take = [&](void **dst) { *dst = p; p += arr; };
+    for (int q = 0; q < 3; q++) take(&g->dEp[q]);
+    for (int b = 0; b < 2; b++)
+        for (int q = 0; q < 3; q++) take(&g->X[b][q]);
+    for (int q = 0; q < 3; q++) take(&g->S[q]);
+    if (cfg->ndim == 2) {
+        for (int q = 0; q < 3; q++) take(&g->Bws[q]);
+        for (int q = 0; q < 3; q++) g->Jf[q] = g->Jt[q] = nullptr;
+    } else {
+        for (int q = 0; q < 3; q++) take(&g->Jf[q]);
+        for (int q = 0; q < 3; q++) take(&g->Jt[q]);
+        for (int q = 0; q < 3; q++) g->Bws[q] = nullptr;
+    }
+    g->partial = (double *)p;
+    p += up((size_t)max_wg(cfg) * 2 * sizeof(double));
+    g->red = (double *)p;
+    for (int q = 0; q < 3; q++) { g->E[q] = g->B[q] = g->J0[q] = nullptr; g->bloc[q] = 0; }
+    fill_coef(cfg, g->cf);
+    fill_coef(cfg, g->cd);
+    *out = g;
+    return MX_OK;
+}
+
+int mx_bind_fields(mx_grid *g, void *const E[3], void *const B[3])
+{
+    if (!g || !E || !B) return fail(MX_EINVAL, "NULL argument");
+    for (int q = 0; q < 3; q++)
+        if (!E[q] || !B[q]) return fail(MX_EINVAL, "field component %d is NULL", q);
+    for (int q = 0; q < 3; q++) { g->E[q] = E[q]; g->B[q] = B[q]; g->bloc[q] = 0; }
+    g->bound = true;
+    return MX_OK;
+}
+
+int mx_set_current(mx_grid *g, void *const J0[3])
+{
+    if (!g) return fail(MX_EINVAL, "grid is NULL");
+    if (!J0) { g->has_j = false; for (int q = 0; q < 3; q++) g->J0[q] = nullptr; return MX_OK; }
+    for (int q = 0; q < 3; q++)
+        if (!J0[q]) return fail(MX_EINVAL, "J0 component %d is NULL", q);
+    for (int q = 0; q < 3; q++) g->J0[q] = J0[q];
+    g->has_j = true;
+    return MX_OK;
+}
+
+int mx_get_step(mx_grid *g, int64_t *n)
+{
+    if (!g || !n) return fail(MX_EINVAL, "NULL argument");
+    *n = g->step;
+    return MX_OK;
+}
+
+int mx_set_step(mx_grid *g, int64_t n)
+{
+    if (!g) return fail(MX_EINVAL, "NULL argument");
+    g->step = n;
+    return MX_OK;
+}
+
+int mx_get_sweeps_per_pass(mx_grid *g, int *k)
+{
+    if (!g || !k) return fail(MX_EINVAL, "NULL argument");
+    *k = g->spp;
+    return MX_OK;
+}
+
+int mx_destroy(mx_grid *g)
+{
+    delete g;
+    return MX_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+const Coef<T> &coef(const mx_grid *g);
+template <>
+const Coef<float> &coef<float>(const mx_grid *g) { return g->cf; }
+template <>
+const Coef<double> &coef<double>(const mx_grid *g) { return g->cd; }
+
+int block_mask_comps(int ndim, int b) { return ndim == 3 ? 7 : (b == 0 ? 3 : 4); }
+
+// Run the sweeps of one solve: x = sum_{j<count} A^j b per block (Alg 1).
+// rhs: the right-hand side (dE' or Ebar).  Writes the per-block result
+// pointers into res[3].  When fuse_E is set and every block finishes in one
+// final pass, E += result is fused into that pass and *e_done is set.
+template <typename T>
+int run_sweeps(mx_grid *g, void *const rhs[3], const int *target_in, bool tolmode, const double *rhsn,
+               void *E_fuse[3], bool *e_done, const T **res, mx_step_stats *st)
+{
+    const mx_config &c = g->cfg;
+    const Coef<T> &k = coef<T>(g);
+    const int nblk = c.ndim == 3 ? 1 : 2;
+    const bool delta = c.form == MX_FORM_DELTA && tolmode;
+    int target[2] = {0, 0}, done[2] = {0, 0}, cur[2] = {-1, -1};
+    bool conv[2] = {false, false};
+    double resid[2] = {0.0, 0.0};
+    bool active_cfg[2];
+    for (int b = 0; b < 2; b++) {
+        active_cfg[b] = b < nblk && (c.ndim == 3 || (c.blocks & (1 << b)));
+        target[b] = active_cfg[b] ? target_in[b] : 0;
+    }
+    *e_done = false;
+    for (;;) {
+        int act = 0, kk = 1 << 30;
+        for (int b = 0; b < nblk; b++)
+            if (active_cfg[b] && done[b] < target[b] && !conv[b]) {
+                act |= 1 << b;
+                kk = std::min(kk, target[b] - done[b]);
+            }
+        if (!act) break;
+        kk = std::min(kk, g->spp);
+        const bool first = (act & 1) ? done[0] == 0 : done[1] == 0;
+        bool all_finish = !tolmode && E_fuse != nullptr;
+        for (int b = 0; b < nblk; b++) {
+            if (!active_cfg[b]) continue;
+            if (!(act & (1 << b)) || done[b] + kk != target[b]) all_finish = false;
+        }
+        int flags = 0;
+        if (first) flags |= SW_FIRST;
+        if (tolmode) flags |= SW_RESID;
+        if (all_finish) flags |= SW_LAST; else flags |= SW_STORE;
+        const int cb = (act & 1) ? cur[0] : cur[1];
+        const int ob = cb == 0 ? 1 : 0;
+        SweepArgs<T> a{};
+        for (int q = 0; q < 3; q++) {
+            a.rhs[q] = (const T *)rhs[q];
+            a.x_in[q] = (const T *)(cb < 0 ? rhs[q] : g->X[cb][q]);
+            a.s_in[q] = (const T *)g->S[q];
+            a.x_out[q] = (T *)g->X[ob][q];
+            a.s_out[q] = (T *)g->S[q];
+            a.E[q] = E_fuse ? (T *)E_fuse[q] : nullptr;
+        }
+        a.partial = g->partial;
+        int nwg = 0;
+        hipError_t e;
+        if (c.ndim == 2) e = launch_sweep2d<T>(k, c.ndim == 3 ? 3 : act, kk, delta, flags, a, g->stream, &nwg);
+        else e = launch_sweep3d<T>(k, delta, flags, a, g->stream, &nwg);
+        if (e != hipSuccess) return fail(MX_EDEVICE, "sweep launch: %s", hipGetErrorString(e));
+        for (int b = 0; b < nblk; b++)
+            if (act & (1 << b)) { done[b] += kk; cur[b] = ob; }
+        if (all_finish) *e_done = true;
+        if (tolmode) {
+            HIPCHK(launch_reduce2(g->partial, nwg, g->red, g->stream));
+            double h[2];
+            HIPCHK(hipMemcpyAsync(h, g->red, sizeof(h), hipMemcpyDeviceToHost, g->stream));
+            HIPCHK(hipStreamSynchronize(g->stream));
+            for (int b = 0; b < nblk; b++) {
+                if (!(act & (1 << b))) continue;
+                resid[b] = std::sqrt(h[b]);
+                if (!std::isfinite(resid[b]))
+                    return fail(MX_ENONFINITE, "step %lld: residual of block %d is not finite", (long long)g->step, b);
+                if (resid[b] <= c.tol * rhsn[b]) conv[b] = true;
+            }
+        }
+    }
+    for (int q = 0; q < 3; q++) {
+        const int b = c.ndim == 3 ? 0 : (q == 2 ? 1 : 0);
+        if (done[b] == 0) res[q] = (const T *)rhs[q];
+        else res[q] = delta ? (const T *)g->S[q] : (const T *)g->X[cur[b]][q];
+    }
+    if (st) {
+        for (int b = 0; b < 2; b++) {
+            st->sweeps[b] = done[b];
+            st->resid[b] = resid[b];
+            st->rhs[b] = rhsn ? rhsn[b] : 0.0;
+            st->nonconverged[b] = tolmode && active_cfg[b] && done[b] > 0 && !conv[b] ? 1 : 0;
+        }
+    }
+    return MX_OK;
+}
+
+template <typename T>
+int step_impl(mx_grid *g, int nsteps, const double *env, const int *replay, mx_step_stats *stats)
+{
+    const mx_config &c = g->cfg;
+    const Coef<T> &k = coef<T>(g);
+    const int nblk = c.ndim == 3 ? 1 : 2;
+    const bool tolmode = c.tol > 0.0 && replay == nullptr;
+    for (int s = 0; s < nsteps; s++) {
+        const double e = env ? env[s] : 0.0;
+        const T env_src = (T)(e * c.four_pi * c.dt);
+        int nwg = 0;
+        double rhsn[2] = {0.0, 0.0};
+        if (c.ndim == 2) {
+            const T *Bin[3];
+            T *Bout[3];
+            for (int q = 0; q < 3; q++) {
+                Bin[q] = (const T *)(g->bloc[q] ? g->Bws[q] : g->B[q]);
+                Bout[q] = (T *)(g->bloc[q] ? g->B[q] : g->Bws[q]);
+            }
+            FrontArgs<T> a{};
+            for (int q = 0; q < 3; q++) {
+                a.E[q] = (const T *)g->E[q];
+                a.B[q] = Bout[q];
+                a.J0[q] = g->has_j ? (const T *)g->J0[q] : nullptr;
+                a.dEp[q] = (T *)g->dEp[q];
+            }
+            a.env_src = env_src;
+            a.partial = tolmode ? g->partial : nullptr;
+            hipError_t er = launch_front2d<T>(k, c.blocks, c.filter_passes, a, Bin, g->stream, &nwg);
+            if (er != hipSuccess) return fail(MX_EDEVICE, "front launch: %s", hipGetErrorString(er));
+            // B components of active blocks now live in the other buffer
+            if (c.blocks & 1) g->bloc[2] ^= 1;
+            if (c.blocks & 2) { g->bloc[0] ^= 1; g->bloc[1] ^= 1; }
+        } else {
+            hipError_t er = launch_faraday3d<T>(k, (const T *const *)g->E, (T *const *)g->B, g->stream);
+            if (er != hipSuccess) return fail(MX_EDEVICE, "faraday launch: %s", hipGetErrorString(er));
+            const T *const *jf = nullptr;
+            if (g->has_j) {
+                jf = (const T *const *)g->J0;
+                if (c.filter_passes > 0) {
+                    er = launch_filter3d<T>(k, c.filter_passes, (const T *const *)g->J0, (T *const *)g->Jf,
+                                            (T *const *)g->Jt, g->stream);
+                    if (er != hipSuccess) return fail(MX_EDEVICE, "filter launch: %s", hipGetErrorString(er));
+                    jf = (const T *const *)g->Jf;
+                }
+            }
+            er = launch_rhs3d<T>(k, (const T *const *)g->B, jf, env_src, (T *const *)g->dEp,
+                                 tolmode ? g->partial : nullptr, g->stream, &nwg);
+            if (er != hipSuccess) return fail(MX_EDEVICE, "rhs launch: %s", hipGetErrorString(er));
+        }
+        if (tolmode) {
+            HIPCHK(launch_reduce2(g->partial, nwg, g->red, g->stream));
+            double h[2];
+            HIPCHK(hipMemcpyAsync(h, g->red, sizeof(h), hipMemcpyDeviceToHost, g->stream));
+            HIPCHK(hipStreamSynchronize(g->stream));
+            for (int b = 0; b < nblk; b++) {
+                rhsn[b] = std::sqrt(h[b]);
+                if (!std::isfinite(rhsn[b]))
+                    return fail(MX_ENONFINITE, "step %lld: norm of dE' is not finite", (long long)g->step);
+            }
+        }
+        int target[2];
+        for (int b = 0; b < 2; b++) {
+            target[b] = replay ? replay[2 * s + b] : c.sweeps;
+            if (!replay && c.lumped) target[b] = 0;
+            if (tolmode && rhsn[b] == 0.0) target[b] = 0;
+            if (target[b] < 0) return fail(MX_EINVAL, "negative replayed sweep count at step %d", s);
+        }
+        const T *res[3];
+        bool e_done = false;
+        mx_step_stats st{};
+        int rc = run_sweeps<T>(g, g->dEp, target, tolmode, rhsn, g->E, &e_done, res,
+                               stats ? &st : nullptr);
+        if (rc) return rc;
+        if (!e_done) {
+            // E += dE per block (the components of inactive 2D blocks are left alone)
+            for (int b = 0; b < nblk; b++) {
+                if (c.ndim == 2 && !(c.blocks & (1 << b))) continue;
+                const int mask = block_mask_comps(c.ndim, b);
+                hipError_t er = launch_update<T>(g->ncell, mask, (T *const *)g->E, res, g->stream);
+                if (er != hipSuccess) return fail(MX_EDEVICE, "update launch: %s", hipGetErrorString(er));
+            }
+        }
+        if (stats) stats[s] = st;
+        g->step++;
+    }
+    // hand the state back in the caller's B buffers
+    if (c.ndim == 2)
+        for (int q = 0; q < 3; q++)
+            if (g->bloc[q]) {
+                HIPCHK(hipMemcpyAsync(g->B[q], g->Bws[q], (size_t)g->ncell * sizeof(T), hipMemcpyDeviceToDevice,
+                                      g->stream));
+                g->bloc[q] = 0;
+            }
+    return MX_OK;
+}
+
+template <typename T>
+int adjoint_impl(mx_grid *g, int nsteps, const double *env, const int *sweeps, void *const Ebar[3],
+                 void *const Bbar[3], void *const dJ0[3])
+{
+    const mx_config &c = g->cfg;
+    const Coef<T> &k = coef<T>(g);
+    for (int s = nsteps - 1; s >= 0; s--) {
+        int target[2] = {sweeps[2 * s], sweeps[2 * s + 1]};
+        const T *v[3];
+        bool e_done = false;
+        // v = P Ebar
+        int rc = run_sweeps<T>(g, Ebar, target, false, nullptr, nullptr, &e_done, v, nullptr);
+        if (rc) return rc;
+        HIPCHK(launch_adj_curlB<T>(k, c.ndim, c.blocks, v, (T *const *)Bbar, g->stream));
+        if (dJ0) {
+            const T scale = (T)(-(env ? env[s] : 0.0) * c.four_pi * c.dt);
+            // filter temporaries: dE' and the running-sum buffers are free here
+            HIPCHK(launch_adj_source<T>(k, c.ndim, c.filter_passes, v, (T *const *)g->dEp, (T *const *)g->S,
+                                        scale, (T *const *)dJ0, g->stream));
+        }
+        HIPCHK(launch_adj_curlE<T>(k, c.ndim, c.blocks, (const T *const *)Bbar, (T *const *)Ebar, g->stream));
+    }
+    return MX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mx_step(mx_grid *g, int nsteps, const double *env, const int *replay, mx_step_stats *stats)
+{
+    if (!g) return fail(MX_EINVAL, "grid is NULL");
+    if (!g->bound) return fail(MX_ESTATE, "mx_step before mx_bind_fields");
+    if (nsteps < 0) return fail(MX_EINVAL, "nsteps must be >= 0");
+    HIPCHK(hipSetDevice(g->device));
+    return g->cfg.dtype == MX_F64 ? step_impl<double>(g, nsteps, env, replay, stats)
+                                  : step_impl<float>(g, nsteps, env, replay, stats);
+}
+
+int mx_adjoint(mx_grid *g, int nsteps, const double *env, const int *sweeps, void *const Ebar[3],
+               void *const Bbar[3], void *const dJ0[3])
+{
+    if (!g || !sweeps || !Ebar || !Bbar) return fail(MX_EINVAL, "NULL argument");
+    if (nsteps < 0) return fail(MX_EINVAL, "nsteps must be >= 0");
+    for (int q = 0; q < 3; q++)
+        if (!Ebar[q] || !Bbar[q] || (dJ0 && !dJ0[q])) return fail(MX_EINVAL, "NULL component");
+    for (int s = 0; s < 2 * nsteps; s++)
+        if (sweeps[s] < 0) return fail(MX_EINVAL, "negative sweep count");
+    HIPCHK(hipSetDevice(g->device));
+    return g->cfg.dtype == MX_F64 ? adjoint_impl<double>(g, nsteps, env, sweeps, Ebar, Bbar, dJ0)
+                                  : adjoint_impl<float>(g, nsteps, env, sweeps, Ebar, Bbar, dJ0);
+}
+
+int mx_sources_assemble(mx_grid *g, int nsrc, int W, const int64_t *origins, const void *shapes,
+                        const void *amps, void *const J0[3])
+{
+    if (!g || !origins || !shapes || !amps || !J0) return fail(MX_EINVAL, "NULL argument");
+    if (g->cfg.ndim != 2) return fail(MX_EINVAL, "source windows are 2D");
+    if (nsrc < 0 || W < 1 || W > g->cfg.n[0] || W > g->cfg.n[1]) return fail(MX_EINVAL, "bad nsrc or W");
+    HIPCHK(hipSetDevice(g->device));
+    const int nx = (int)g->cfg.n[0], ny = (int)g->cfg.n[1];
+    if (g->cfg.dtype == MX_F64)
+        HIPCHK(launch_sources<double>(nx, ny, nsrc, W, origins, (const double *)shapes, (const double *)amps,
+                                      (double *const *)J0, nullptr, nullptr, false, g->stream));
+    else
+        HIPCHK(launch_sources<float>(nx, ny, nsrc, W, origins, (const float *)shapes, (const float *)amps,
+                                     (float *const *)J0, nullptr, nullptr, false, g->stream));
+    return MX_OK;
+}
+
+int mx_sources_project(mx_grid *g, int nsrc, int W, const int64_t *origins, const void *shapes,
+                       void *const G[3], void *grad)
+{
+    if (!g || !origins || !shapes || !G || !grad) return fail(MX_EINVAL, "NULL argument");
+    if (g->cfg.ndim != 2) return fail(MX_EINVAL, "source windows are 2D");
+    if (nsrc < 0 || W < 1 || W > g->cfg.n[0] || W > g->cfg.n[1]) return fail(MX_EINVAL, "bad nsrc or W");
+    if (nsrc == 0) return MX_OK;
+    HIPCHK(hipSetDevice(g->device));
+    const int nx = (int)g->cfg.n[0], ny = (int)g->cfg.n[1];
+    if (g->cfg.dtype == MX_F64)
+        HIPCHK(launch_sources<double>(nx, ny, nsrc, W, origins, (const double *)shapes, nullptr, nullptr,
+                                      (double *const *)G, (double *)grad, true, g->stream));
+    else
+        HIPCHK(launch_sources<float>(nx, ny, nsrc, W, origins, (const float *)shapes, nullptr, nullptr,
+                                     (float *const *)G, (float *)grad, true, g->stream));
+    return MX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+// Internal declarations shared by the host library and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mx.h"
+
+namespace mx {
+
+// Per-grid scalar coefficients, computed on the host in FP64 and rounded
+// once to the kernel type.  r_i = (c dt / d_i)^2, r_ij = (c dt)^2/(d_i d_j).
+template <typename T>
+struct Coef {
+    int nx, ny, nz;
+    T tdx, tdy, tdz;            // dt / d_i (curl prefactors)
+    T src;                      // 4 pi dt (current prefactor)
+    // 2D A (eqs matrixA_*_2d): TE  x+ = b + cxx Dyy x + cxy DxDy y
+    //                                y+ = b + cyy Dxx y + cxy DxDy x
+    //                          TM  z+ = b + czx Dxx z + czy Dyy z + czz DxxDyy z
+    // 3D A (eqs matrixA_*): diagonal blocks a[i][0..2] = ((r_j-1)/6, (r_k-1)/6,
+    // (r_j+r_k-1)/36) for the (j, k) axes cyclic after i; off-diagonal
+    // o[i][j] = -r_ij / 6 multiplying Dbar_i Dbar_j alpha_k.
+    T cxx, cyy, cxy, czx, czy, czz;
+    T a3[3][3];
+    T o3[3];                    // o3[0] = -r_yz/6 (yz pair), o3[1] = -r_zx/6, o3[2] = -r_xy/6
+    int lumped;
+};
+
+// Sweep pass flags (runtime, uniform per launch)
+enum : int {
+    SW_FIRST = 1,     // iterate input is dE' itself (x_0 = dE')
+    SW_LAST = 2,      // add the final iterate (or sum) to E
+    SW_RESID = 4,     // accumulate FP64 norm of the last sweep's step
+    SW_STORE = 8,     // store the final iterate (and sum) for a later pass
+};
+
+template <typename T>
+struct SweepArgs {
+    const T *x_in[3];     // iterate (standard) or delta (delta form), with halo
+    const T *rhs[3];      // dE' (standard form)
+    const T *s_in[3];     // running sum (delta form)
+    T *x_out[3];
+    T *s_out[3];
+    T *E[3];
+    double *partial;      // per-workgroup partial sums [nblocks][2] (TE, TM)
+};
+
+template <typename T>
+struct FrontArgs {
+    const T *E[3];
+    T *B[3];
+    const T *J0[3];       // may be null
+    T env_src;            // env * 4 pi dt
+    T *dEp[3];
+    double *partial;      // per-workgroup ||dE'||^2 partials [nblocks][2], or null
+};
+
+// 2D launchers (k2d.hip)
+template <typename T>
+hipError_t launch_front2d(const Coef<T> &c, int blocks, int filter_passes, const FrontArgs<T> &a,
+                          const T *const Bin[3], hipStream_t s, int *nwg);
+template <typename T>
+hipError_t launch_sweep2d(const Coef<T> &c, int blocks, int k, bool delta, int flags,
+                          const SweepArgs<T> &a, hipStream_t s, int *nwg);
+template <typename T>
+hipError_t launch_update(int64_t n, int comp_mask, T *const E[3], const T *const X[3], hipStream_t s);
+
+// 3D launchers (k3d.hip)
+template <typename T>
+hipError_t launch_filter3d(const Coef<T> &c, int passes, const T *const J0[3], T *const Jf[3],
+                           T *const tmp[3], hipStream_t s);
+template <typename T>
+hipError_t launch_faraday3d(const Coef<T> &c, const T *const E[3], T *const B[3], hipStream_t s);
+template <typename T>
+hipError_t launch_rhs3d(const Coef<T> &c, const T *const B[3], const T *const Jf[3], T env_src,
+                        T *const dEp[3], double *partial, hipStream_t s, int *nwg);
+template <typename T>
+hipError_t launch_sweep3d(const Coef<T> &c, bool delta, int flags, const SweepArgs<T> &a,
+                          hipStream_t s, int *nwg);
+
+// FP64 partial-sum reduction: out[0..1] = sum over nwg rows of partial[row][0..1]
+hipError_t launch_reduce2(const double *partial, int nwg, double *out, hipStream_t s);
+
+// Adjoint helpers (kadj.hip)
+template <typename T>
+hipError_t launch_adj_curlB(const Coef<T> &c, int ndim, int blocks, const T *const v[3],
+                            T *const Bbar[3], hipStream_t s);
+template <typename T>
+hipError_t launch_adj_curlE(const Coef<T> &c, int ndim, int blocks, const T *const Bbar[3],
+                            T *const Ebar[3], hipStream_t s);
+template <typename T>
+hipError_t launch_adj_source(const Coef<T> &c, int ndim, int passes, const T *const v[3],
+                             T *const tmp1[3], T *const tmp2[3], T scale, T *const dJ0[3],
+                             hipStream_t s);
+template <typename T>
+hipError_t launch_sources(int nx, int ny, int nsrc, int W, const int64_t *origins, const T *shapes,
+                          const T *amps, T *const J0[3], T *const G[3], T *grad, bool project,
+                          hipStream_t s);
+
+}  // namespace mx
