@@ -145,6 +145,26 @@ int mx_get_sweeps_per_pass(mx_grid *g, int *k);
 int mx_destroy(mx_grid *g);
 
 /* ------------------------------------------------------------------------
+ * Per-kernel timing.  While enabled, every launch of mx_step / mx_adjoint is
+ * bracketed by HIP events recorded on the grid's stream, and its algorithmic
+ * HBM traffic (each array a kernel must read or write, counted once per
+ * touched cell) is added to its category.  mx_profile_enable resets the
+ * counters; mx_profile_read waits for the stream and sums the event times.
+ * ------------------------------------------------------------------------ */
+#define MX_PROF_FRONT   0   /* filter + Faraday + auxiliary increment */
+#define MX_PROF_SWEEP   1   /* mass-matrix sweep passes (E increment fused) */
+#define MX_PROF_OTHER   2   /* separate E increments, FP64 reductions, copies */
+#define MX_PROF_ADJOINT 3   /* transposed curls and the filter of the adjoint */
+typedef struct mx_profile {
+    int64_t launches[4];
+    double ms[4];         /* summed kernel time per category */
+    double bytes[4];      /* summed algorithmic bytes per category */
+} mx_profile;
+
+int mx_profile_enable(mx_grid *g, int on);
+int mx_profile_read(mx_grid *g, mx_profile *out);
+
+/* ------------------------------------------------------------------------
  * Transposed (adjoint) step.  The step is linear in (E, B, J0):
  *   B+ = B - dt K E,   E+ = E + P (dt K^T Lambda B+ - 4 pi dt env F J0),
  * K the E->B curl of eqs faraday_*, K^T the B->E curl of eqs ampere_aux_*,

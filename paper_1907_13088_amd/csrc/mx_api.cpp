@@ -83,7 +83,47 @@ struct mx_grid {
     int spp;
     Coef<float> cf;
     Coef<double> cd;
+    // timing (mx_profile_*)
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<int> ev_cat;          // category per event pair
+    int64_t launches[4] = {0, 0, 0, 0};
+    double bytes[4] = {0, 0, 0, 0};
 };
+
+namespace {
+
+// bracket one launch with events when profiling is on
+struct ProfScope {
+    mx_grid *g;
+    int cat;
+    hipEvent_t e1 = nullptr;
+    ProfScope(mx_grid *g_, int cat_, double bytes) : g(g_), cat(cat_)
+    {
+        if (!g->prof) return;
+        if (g->ev_used + 2 > g->ev_pool.size()) {
+            for (int i = 0; i < 64; i++) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess) { g->prof = false; return; }
+                g->ev_pool.push_back(e);
+            }
+        }
+        hipEvent_t e0 = g->ev_pool[g->ev_used];
+        e1 = g->ev_pool[g->ev_used + 1];
+        g->ev_used += 2;
+        g->ev_cat.push_back(cat);
+        hipEventRecord(e0, g->stream);
+        g->launches[cat] += 1;
+        g->bytes[cat] += bytes;
+    }
+    ~ProfScope()
+    {
+        if (e1) hipEventRecord(e1, g->stream);
+    }
+};
+
+}  // namespace
 
 template <typename T>
 static void fill_coef(const mx_config *c, Coef<T> &k)
@@ -280,7 +320,33 @@ int mx_get_sweeps_per_pass(mx_grid *g, int *k)
 
 int mx_destroy(mx_grid *g)
 {
+    if (!g) return MX_OK;
+    for (hipEvent_t e : g->ev_pool) hipEventDestroy(e);
     delete g;
+    return MX_OK;
+}
+
+int mx_profile_enable(mx_grid *g, int on)
+{
+    if (!g) return fail(MX_EINVAL, "grid is NULL");
+    g->prof = on != 0;
+    g->ev_used = 0;
+    g->ev_cat.clear();
+    for (int i = 0; i < 4; i++) { g->launches[i] = 0; g->bytes[i] = 0.0; }
+    return MX_OK;
+}
+
+int mx_profile_read(mx_grid *g, mx_profile *out)
+{
+    if (!g || !out) return fail(MX_EINVAL, "NULL argument");
+    HIPCHK(hipSetDevice(g->device));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    for (int i = 0; i < 4; i++) { out->launches[i] = g->launches[i]; out->bytes[i] = g->bytes[i]; out->ms[i] = 0.0; }
+    for (size_t p = 0; p < g->ev_cat.size(); p++) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, g->ev_pool[2 * p], g->ev_pool[2 * p + 1]));
+        out->ms[g->ev_cat[p]] += ms;
+    }
     return MX_OK;
 }
 
@@ -351,14 +417,27 @@ int run_sweeps(mx_grid *g, void *const rhs[3], const int *target_in, bool tolmod
         a.partial = g->partial;
         int nwg = 0;
         hipError_t e;
-        if (c.ndim == 2) e = launch_sweep2d<T>(k, c.ndim == 3 ? 3 : act, kk, delta, flags, a, g->stream, &nwg);
-        else e = launch_sweep3d<T>(k, delta, flags, a, g->stream, &nwg);
+        {
+            // arrays touched per component: the iterate (or dE' on the first
+            // pass) with halo, dE' (standard form), the running sum (delta
+            // form), the stored iterate/sum, or E read and written
+            int arrs;
+            if (!delta) arrs = (first ? 1 : 2) + ((flags & SW_LAST) ? 2 : 1);
+            else arrs = (first ? 1 : 2) + ((flags & SW_LAST) ? 2 : 2);
+            const int ncomp = c.ndim == 3 ? 3 : ((act & 1) ? 2 : 0) + ((act & 2) ? 1 : 0);
+            ProfScope ps(g, MX_PROF_SWEEP, (double)g->ncell * sizeof(T) * arrs * ncomp);
+            if (c.ndim == 2) e = launch_sweep2d<T>(k, act, kk, delta, flags, a, g->stream, &nwg);
+            else e = launch_sweep3d<T>(k, delta, flags, a, g->stream, &nwg);
+        }
         if (e != hipSuccess) return fail(MX_EDEVICE, "sweep launch: %s", hipGetErrorString(e));
         for (int b = 0; b < nblk; b++)
             if (act & (1 << b)) { done[b] += kk; cur[b] = ob; }
         if (all_finish) *e_done = true;
         if (tolmode) {
-            HIPCHK(launch_reduce2(g->partial, nwg, g->red, g->stream));
+            {
+                ProfScope ps(g, MX_PROF_OTHER, 0.0);
+                HIPCHK(launch_reduce2(g->partial, nwg, g->red, g->stream));
+            }
             double h[2];
             HIPCHK(hipMemcpyAsync(h, g->red, sizeof(h), hipMemcpyDeviceToHost, g->stream));
             HIPCHK(hipStreamSynchronize(g->stream));
@@ -415,30 +494,47 @@ int step_impl(mx_grid *g, int nsteps, const double *env, const int *replay, mx_s
             }
             a.env_src = env_src;
             a.partial = tolmode ? g->partial : nullptr;
-            hipError_t er = launch_front2d<T>(k, c.blocks, c.filter_passes, a, Bin, g->stream, &nwg);
+            const double fb = (double)g->ncell * sizeof(T) *
+                              (((c.blocks & 1) ? (g->has_j ? 8 : 6) : 0) + ((c.blocks & 2) ? (g->has_j ? 7 : 6) : 0));
+            hipError_t er;
+            {
+                ProfScope ps(g, MX_PROF_FRONT, fb);
+                er = launch_front2d<T>(k, c.blocks, c.filter_passes, a, Bin, g->stream, &nwg);
+            }
             if (er != hipSuccess) return fail(MX_EDEVICE, "front launch: %s", hipGetErrorString(er));
             // B components of active blocks now live in the other buffer
             if (c.blocks & 1) g->bloc[2] ^= 1;
             if (c.blocks & 2) { g->bloc[0] ^= 1; g->bloc[1] ^= 1; }
         } else {
-            hipError_t er = launch_faraday3d<T>(k, (const T *const *)g->E, (T *const *)g->B, g->stream);
+            hipError_t er;
+            {
+                ProfScope ps(g, MX_PROF_FRONT, (double)g->ncell * sizeof(T) * 9);
+                er = launch_faraday3d<T>(k, (const T *const *)g->E, (T *const *)g->B, g->stream);
+            }
             if (er != hipSuccess) return fail(MX_EDEVICE, "faraday launch: %s", hipGetErrorString(er));
             const T *const *jf = nullptr;
             if (g->has_j) {
                 jf = (const T *const *)g->J0;
                 if (c.filter_passes > 0) {
+                    ProfScope ps(g, MX_PROF_FRONT, (double)g->ncell * sizeof(T) * 6 * 3 * c.filter_passes);
                     er = launch_filter3d<T>(k, c.filter_passes, (const T *const *)g->J0, (T *const *)g->Jf,
                                             (T *const *)g->Jt, g->stream);
                     if (er != hipSuccess) return fail(MX_EDEVICE, "filter launch: %s", hipGetErrorString(er));
                     jf = (const T *const *)g->Jf;
                 }
             }
-            er = launch_rhs3d<T>(k, (const T *const *)g->B, jf, env_src, (T *const *)g->dEp,
-                                 tolmode ? g->partial : nullptr, g->stream, &nwg);
+            {
+                ProfScope ps(g, MX_PROF_FRONT, (double)g->ncell * sizeof(T) * (jf ? 9 : 6));
+                er = launch_rhs3d<T>(k, (const T *const *)g->B, jf, env_src, (T *const *)g->dEp,
+                                     tolmode ? g->partial : nullptr, g->stream, &nwg);
+            }
             if (er != hipSuccess) return fail(MX_EDEVICE, "rhs launch: %s", hipGetErrorString(er));
         }
         if (tolmode) {
-            HIPCHK(launch_reduce2(g->partial, nwg, g->red, g->stream));
+            {
+                ProfScope ps(g, MX_PROF_OTHER, 0.0);
+                HIPCHK(launch_reduce2(g->partial, nwg, g->red, g->stream));
+            }
             double h[2];
             HIPCHK(hipMemcpyAsync(h, g->red, sizeof(h), hipMemcpyDeviceToHost, g->stream));
             HIPCHK(hipStreamSynchronize(g->stream));
@@ -466,7 +562,11 @@ int step_impl(mx_grid *g, int nsteps, const double *env, const int *replay, mx_s
             for (int b = 0; b < nblk; b++) {
                 if (c.ndim == 2 && !(c.blocks & (1 << b))) continue;
                 const int mask = block_mask_comps(c.ndim, b);
-                hipError_t er = launch_update<T>(g->ncell, mask, (T *const *)g->E, res, g->stream);
+                hipError_t er;
+                {
+                    ProfScope ps(g, MX_PROF_OTHER, (double)g->ncell * sizeof(T) * 3 * (mask == 7 ? 3 : mask == 3 ? 2 : 1));
+                    er = launch_update<T>(g->ncell, mask, (T *const *)g->E, res, g->stream);
+                }
                 if (er != hipSuccess) return fail(MX_EDEVICE, "update launch: %s", hipGetErrorString(er));
             }
         }
@@ -477,6 +577,7 @@ int step_impl(mx_grid *g, int nsteps, const double *env, const int *replay, mx_s
     if (c.ndim == 2)
         for (int q = 0; q < 3; q++)
             if (g->bloc[q]) {
+                ProfScope ps(g, MX_PROF_OTHER, 2.0 * g->ncell * sizeof(T));
                 HIPCHK(hipMemcpyAsync(g->B[q], g->Bws[q], (size_t)g->ncell * sizeof(T), hipMemcpyDeviceToDevice,
                                       g->stream));
                 g->bloc[q] = 0;
@@ -497,14 +598,22 @@ int adjoint_impl(mx_grid *g, int nsteps, const double *env, const int *sweeps, v
         // v = P Ebar
         int rc = run_sweeps<T>(g, Ebar, target, false, nullptr, nullptr, &e_done, v, nullptr);
         if (rc) return rc;
-        HIPCHK(launch_adj_curlB<T>(k, c.ndim, c.blocks, v, (T *const *)Bbar, g->stream));
+        const double arr = (double)g->ncell * sizeof(T);
+        {
+            ProfScope ps(g, MX_PROF_ADJOINT, arr * 9);
+            HIPCHK(launch_adj_curlB<T>(k, c.ndim, c.blocks, v, (T *const *)Bbar, g->stream));
+        }
         if (dJ0) {
             const T scale = (T)(-(env ? env[s] : 0.0) * c.four_pi * c.dt);
             // filter temporaries: dE' and the running-sum buffers are free here
+            ProfScope ps(g, MX_PROF_ADJOINT, arr * 3 * (2 * c.ndim * c.filter_passes + 3));
             HIPCHK(launch_adj_source<T>(k, c.ndim, c.filter_passes, v, (T *const *)g->dEp, (T *const *)g->S,
                                         scale, (T *const *)dJ0, g->stream));
         }
-        HIPCHK(launch_adj_curlE<T>(k, c.ndim, c.blocks, (const T *const *)Bbar, (T *const *)Ebar, g->stream));
+        {
+            ProfScope ps(g, MX_PROF_ADJOINT, arr * 9);
+            HIPCHK(launch_adj_curlE<T>(k, c.ndim, c.blocks, (const T *const *)Bbar, (T *const *)Ebar, g->stream));
+        }
     }
     return MX_OK;
 }

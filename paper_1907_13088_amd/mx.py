@@ -22,7 +22,7 @@ MX_TE, MX_TM, MX_ALL = 1, 2, 3
 FORM_STANDARD, FORM_DELTA = 0, 1
 WARN_NOCONV_GUARANTEE = 1
 
-EXPORTS = ["mx_last_error", "mx_config_default", "mx_validate", "mx_workspace_size", "mx_init",
+EXPORTS = ["mx_profile_enable", "mx_profile_read", "mx_last_error", "mx_config_default", "mx_validate", "mx_workspace_size", "mx_init",
            "mx_bind_fields", "mx_set_current", "mx_step", "mx_get_step", "mx_set_step",
            "mx_get_sweeps_per_pass", "mx_destroy", "mx_adjoint", "mx_sources_assemble",
            "mx_sources_project", "mx_batch_workspace_size", "mx_batch_init", "mx_batch_bind",
@@ -40,6 +40,13 @@ class CConfig(C.Structure):
                 ("dtype", C.c_int), ("blocks", C.c_int), ("sweeps", C.c_int), ("tol", C.c_double),
                 ("filter_passes", C.c_int), ("lumped", C.c_int), ("four_pi", C.c_double),
                 ("form", C.c_int), ("sweeps_per_pass", C.c_int)]
+
+
+class CProfile(C.Structure):
+    _fields_ = [("launches", C.c_int64 * 4), ("ms", C.c_double * 4), ("bytes", C.c_double * 4)]
+
+
+PROF_CATEGORIES = ("front", "sweep", "other", "adjoint")
 
 
 class CStats(C.Structure):
@@ -72,6 +79,8 @@ def lib():
         L.mx_set_step.argtypes = [vp, C.c_int64]
         L.mx_get_sweeps_per_pass.argtypes = [vp, P(C.c_int)]
         L.mx_destroy.argtypes = [vp]
+        L.mx_profile_enable.argtypes = [vp, C.c_int]
+        L.mx_profile_read.argtypes = [vp, P(CProfile)]
         L.mx_adjoint.argtypes = [vp, C.c_int, P(C.c_double), P(C.c_int), P(vp), P(vp), P(vp)]
         L.mx_sources_assemble.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, P(vp)]
         L.mx_sources_project.argtypes = [vp, C.c_int, C.c_int, vp, vp, P(vp), vp]
@@ -234,6 +243,15 @@ class Grid:
         nsrc, W = int(shapes.shape[0]), int(shapes.shape[-1])
         _check(lib().mx_sources_project(self.h, nsrc, W, C.c_void_p(origins.data_ptr()),
                                         C.c_void_p(shapes.data_ptr()), _ptrs(G), C.c_void_p(grad.data_ptr())))
+
+    def profile_enable(self, on: bool = True):
+        _check(lib().mx_profile_enable(self.h, int(bool(on))))
+
+    def profile_read(self) -> dict:
+        p = CProfile()
+        _check(lib().mx_profile_read(self.h, C.byref(p)))
+        return {name: {"launches": int(p.launches[i]), "ms": float(p.ms[i]), "bytes": float(p.bytes[i])}
+                for i, name in enumerate(PROF_CATEGORIES)}
 
     @property
     def step_count(self) -> int:
