@@ -86,6 +86,7 @@ typedef struct mx_config {
     double four_pi;       /* source constant, 4 pi in Gaussian units */
     int form;             /* MX_FORM_STANDARD or MX_FORM_DELTA */
     int sweeps_per_pass;  /* sweeps fused per pass over HBM; 0 = library choice */
+    int variant;          /* 2D sweep kernel: 0 library choice, 1 LDS tile, 2 row streaming */
 } mx_config;
 
 typedef struct mx_step_stats {

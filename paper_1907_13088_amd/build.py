@@ -14,11 +14,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmx.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["k2d.hip", "k3d.hip", "kadj.hip", "kbatch.hip", "mx_api.cpp"]
+SOURCES = ["k2d.hip", "k2f.hip", "k2s.hip", "k2s_f32.hip", "k2s_f32d.hip", "k2s_f64.hip", "k2s_f64d.hip", "k3d.hip", "kadj.hip", "kbatch.hip", "mx_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # packed FP32 VALU forms stay off: plain FP32 VALU only
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # no automatic contraction: FMAs are written out where intended, so
+         # every schedule of the same stencil rounds identically
+         "-ffp-contract=off",
          "-Wno-unused-command-line-argument"]
 
 
@@ -36,12 +39,12 @@ def build(force: bool = True, verbose: bool = False) -> str:
     """Compile every source for gfx950 and link libmx.so (always rebuilds
     when force is set)."""
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    deps = [os.path.join(CSRC, s) for s in srcs] + [os.path.join(CSRC, "mx_internal.h"),
+    deps = [os.path.join(CSRC, s) for s in srcs] + [os.path.join(CSRC, h) for h in ("mx_internal.h", "k2s_impl.h", "stencil2d.h")] + [
                                                     os.path.join(HERE, "..", "include", "mx.h")]
     if not force and os.path.exists(OUT) and all(os.path.getmtime(OUT) >= os.path.getmtime(d) for d in deps):
         return OUT
     os.makedirs(OBJ, exist_ok=True)
-    jobs = min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
+    jobs = min(len(srcs), max(1, min(16, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + ".tmp"

@@ -47,13 +47,17 @@ int64_t max_wg(const mx_config *c)
     const int64_t nx = c->n[0], ny = c->n[1], nz = c->ndim == 3 ? c->n[2] : 1;
     // 2D front tiles 64x16, 2D sweep tiles 64x8 at the smallest, 3D 64x4 per plane
     const int64_t a = ((nx + 63) / 64) * ((ny + 3) / 4) * nz;
-    return a;
+    // the streaming sweep launches at most one workgroup per (strip, row)
+    const int64_t b = ((nx + 239) / 240 + 1) * ny;
+    return std::max(a, b);
 }
 
 int default_spp(const mx_config *c)
 {
     if (c->ndim == 3) return 1;
-    return c->dtype == MX_F64 ? 4 : 5;
+    const bool stream = c->variant != 1;
+    if (c->dtype == MX_F64) return stream ? (c->blocks == MX_ALL ? 3 : 4) : 4;
+    return stream ? 7 : 5;
 }
 
 // number of full-grid arrays in the workspace
@@ -81,6 +85,7 @@ struct mx_grid {
     double *partial;      // device
     double *red;          // device, 2 doubles
     int spp;
+    int variant;          // 2D sweep kernel in use: 1 LDS tile, 2 row streaming
     Coef<float> cf;
     Coef<double> cd;
     // timing (mx_profile_*)
@@ -199,6 +204,7 @@ int mx_validate(const mx_config *c, int *warn)
     if (!std::isfinite(c->four_pi)) return fail(MX_EINVAL, "four_pi must be finite");
     if (c->form != MX_FORM_STANDARD && c->form != MX_FORM_DELTA) return fail(MX_EINVAL, "bad form");
     if (c->sweeps_per_pass < 0 || c->sweeps_per_pass > 8) return fail(MX_EINVAL, "sweeps_per_pass must be in [0, 8]");
+    if (c->variant < 0 || c->variant > 2) return fail(MX_EINVAL, "variant must be 0, 1 or 2");
     if (c->ndim == 3 && c->sweeps_per_pass > 1) return fail(MX_EINVAL, "3D grids run one sweep per pass");
     if (!(c->dt > 0.0) || !std::isfinite(c->dt)) return fail(MX_EINVAL, "dt must be positive and finite");
     double s = 0.0;
@@ -250,6 +256,7 @@ int mx_init(const mx_config *cfg, void *stream, void *workspace, size_t workspac
     g->step = 0;
     g->bound = false;
     g->has_j = false;
+    g->variant = cfg->variant > 0 ? cfg->variant : 2;
     g->spp = cfg->sweeps_per_pass > 0 ? cfg->sweeps_per_pass : default_spp(cfg);
     const size_t arr = up((size_t)g->ncell * elem_of(cfg));
     char *p = g->ws;
@@ -426,7 +433,8 @@ int run_sweeps(mx_grid *g, void *const rhs[3], const int *target_in, bool tolmod
             else arrs = (first ? 1 : 2) + ((flags & SW_LAST) ? 2 : 2);
             const int ncomp = c.ndim == 3 ? 3 : ((act & 1) ? 2 : 0) + ((act & 2) ? 1 : 0);
             ProfScope ps(g, MX_PROF_SWEEP, (double)g->ncell * sizeof(T) * arrs * ncomp);
-            if (c.ndim == 2) e = launch_sweep2d<T>(k, act, kk, delta, flags, a, g->stream, &nwg);
+            if (c.ndim == 2 && g->variant == 1) e = launch_sweep2d<T>(k, act, kk, delta, flags, a, g->stream, &nwg);
+            else if (c.ndim == 2) e = launch_stream2d<T>(k, act, kk, delta, flags, a, g->stream, &nwg, 0);
             else e = launch_sweep3d<T>(k, delta, flags, a, g->stream, &nwg);
         }
         if (e != hipSuccess) return fail(MX_EDEVICE, "sweep launch: %s", hipGetErrorString(e));
@@ -499,7 +507,7 @@ int step_impl(mx_grid *g, int nsteps, const double *env, const int *replay, mx_s
             hipError_t er;
             {
                 ProfScope ps(g, MX_PROF_FRONT, fb);
-                er = launch_front2d<T>(k, c.blocks, c.filter_passes, a, Bin, g->stream, &nwg);
+                er = launch_front_stream2d<T>(k, c.blocks, c.filter_passes, a, Bin, g->stream, &nwg);
             }
             if (er != hipSuccess) return fail(MX_EDEVICE, "front launch: %s", hipGetErrorString(er));
             // B components of active blocks now live in the other buffer

@@ -58,11 +58,14 @@ struct FrontArgs {
 
 // 2D launchers (k2d.hip)
 template <typename T>
-hipError_t launch_front2d(const Coef<T> &c, int blocks, int filter_passes, const FrontArgs<T> &a,
-                          const T *const Bin[3], hipStream_t s, int *nwg);
+hipError_t launch_front_stream2d(const Coef<T> &c, int blocks, int filter_passes, const FrontArgs<T> &a,
+                                 const T *const Bin[3], hipStream_t s, int *nwg);
 template <typename T>
 hipError_t launch_sweep2d(const Coef<T> &c, int blocks, int k, bool delta, int flags,
                           const SweepArgs<T> &a, hipStream_t s, int *nwg);
+template <typename T>
+hipError_t launch_stream2d(const Coef<T> &c, int blocks, int k, bool delta, int flags, const SweepArgs<T> &a,
+                           hipStream_t s, int *nwg, int slots);
 template <typename T>
 hipError_t launch_update(int64_t n, int comp_mask, T *const E[3], const T *const X[3], hipStream_t s);
 

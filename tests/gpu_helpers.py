@@ -26,18 +26,18 @@ def to_np(ts):
 
 
 def gpu_config(w, dtype=None, spp=0, form=mx.FORM_STANDARD, sweeps=None, tol=None, blocks=None,
-               lumped=False):
+               lumped=False, variant=0):
     n = w.shape[::-1]
     return mx.make_config(w.ndim, n, w.dt, w.d, dtype or w.dtype, blocks if blocks is not None else w.blocks,
                           w.sweeps if sweeps is None else sweeps, w.tol if tol is None else tol,
-                          w.filter_passes, lumped=lumped, form=form, sweeps_per_pass=spp)
+                          w.filter_passes, lumped=lumped, form=form, sweeps_per_pass=spp, variant=variant)
 
 
 def run_gpu(w, nsteps, dtype=None, spp=0, form=mx.FORM_STANDARD, replay=None, sweeps=None, tol=None,
-            blocks=None, lumped=False, E=None, B=None):
+            blocks=None, lumped=False, E=None, B=None, variant=0):
     import torch
     dt_ = dtype or w.dtype
-    cfg = gpu_config(w, dt_, spp, form, sweeps, tol, blocks, lumped)
+    cfg = gpu_config(w, dt_, spp, form, sweeps, tol, blocks, lumped, variant)
     g = mx.Grid(cfg)
     Et = torch_fields(w.E if E is None else E, dt_)
     Bt = torch_fields(w.B if B is None else B, dt_)

@@ -49,29 +49,32 @@ def test_te_planewave_fp64_tolerance_replay_and_decisions():
     assert all(s.sweeps[0] > 20 for s in sto)
 
 
+@pytest.mark.parametrize("variant", [mx.VARIANT_TILE, mx.VARIANT_STREAM])
 @pytest.mark.parametrize("spp", [1, 2, 3, 4, 5, 6, 7, 8])
-def test_modes_fp64_every_pass_depth(small_modes, spp):
+def test_modes_fp64_every_pass_depth(small_modes, spp, variant):
     w = small_modes
     nsteps = 12
-    Eg, Bg, _, k = run_gpu(w, nsteps, spp=spp)
+    Eg, Bg, _, k = run_gpu(w, nsteps, spp=spp, variant=variant)
     assert k == spp
     Eo, Bo, _ = run_oracle(w, nsteps)
     e = rel_err(Eg + Bg, Eo + Bo)
-    log(f"spp={spp} fp64 errors {max(e):.3e}")
+    log(f"variant={variant} spp={spp} fp64 errors {max(e):.3e}")
     assert max(e) < 1e-12
 
 
-def test_pass_depth_invariance_is_bitwise(small_modes):
-    """Fusing k sweeps per pass changes where iterates live, not the arithmetic."""
+def test_pass_depth_and_kernel_invariance_is_bitwise(small_modes):
+    """Fusing k sweeps per pass, and the tile or streaming schedule, change
+    where iterates live, not the arithmetic: FP32 results are bitwise equal."""
     w = small_modes
     ref_out = None
-    for spp in (1, 3, 5, 8):
-        Eg, Bg, _, _ = run_gpu(w, 6, dtype="f32", spp=spp)
-        if ref_out is None:
-            ref_out = (Eg, Bg)
-        else:
-            for a, b in zip(Eg + Bg, ref_out[0] + ref_out[1]):
-                assert np.array_equal(a, b)
+    for variant in (mx.VARIANT_TILE, mx.VARIANT_STREAM):
+        for spp in (1, 3, 5, 8):
+            Eg, Bg, _, _ = run_gpu(w, 6, dtype="f32", spp=spp, variant=variant)
+            if ref_out is None:
+                ref_out = (Eg, Bg)
+            else:
+                for a, b in zip(Eg + Bg, ref_out[0] + ref_out[1]):
+                    assert np.array_equal(a, b), (variant, spp)
 
 
 def test_modes_fp32_within_tolerance(small_modes):
@@ -109,17 +112,18 @@ def test_lumped_yee(small_modes):
     assert all(s.sweeps == (0, 0) for s in st)
 
 
+@pytest.mark.parametrize("variant", [mx.VARIANT_TILE, mx.VARIANT_STREAM])
 @pytest.mark.parametrize("form", [mx.FORM_STANDARD, mx.FORM_DELTA])
-def test_tolerance_mode_small(small_modes, form):
+def test_tolerance_mode_small(small_modes, form, variant):
     w = small_modes
     nsteps = 6
     tol = 1e-9
-    Eg, Bg, stg, spp = run_gpu(w, nsteps, tol=tol, sweeps=300, form=form)
+    Eg, Bg, stg, spp = run_gpu(w, nsteps, tol=tol, sweeps=300, form=form, variant=variant)
     Eo, Bo, sto = run_oracle(w, nsteps, tol=tol, sweeps=300, check_every=spp)
     for a, b in zip(stg, sto):
         assert abs(a.sweeps[0] - b.sweeps[0]) <= spp and abs(a.sweeps[1] - b.sweeps[1]) <= spp
         assert a.rhs[0] == pytest.approx(b.rhs[0], rel=1e-12)
-    Eg, Bg, _, _ = run_gpu(w, nsteps, replay=[s.sweeps for s in sto], form=form)
+    Eg, Bg, _, _ = run_gpu(w, nsteps, replay=[s.sweeps for s in sto], form=form, variant=variant)
     assert max(rel_err(Eg + Bg, Eo + Bo)) < 1e-12
 
 
@@ -170,13 +174,14 @@ def test_nonfinite_field_is_reported():
     assert ei.value.code == mx.MX_ENONFINITE
 
 
-def test_tiny_grids():
+@pytest.mark.parametrize("variant", [mx.VARIANT_TILE, mx.VARIANT_STREAM])
+def test_tiny_grids(variant):
     """Grids smaller than one tile (wrap-around halos many times over)."""
-    for n in ((1, 1), (2, 3), (5, 4), (7, 1)):
+    for n in ((1, 1), (2, 3), (5, 4), (7, 1), (300, 2)):
         w = I.modes_2d(n, nmodes=0, npulses=0, steps=3, seed=3, dtype="f64")
         rng = np.random.default_rng(1)
         w.E = [rng.normal(size=w.shape) for _ in range(3)]
         w.B = [rng.normal(size=w.shape) for _ in range(3)]
-        Eg, Bg, _, _ = run_gpu(w, 3, spp=4)
+        Eg, Bg, _, _ = run_gpu(w, 3, spp=4, variant=variant)
         Eo, Bo, _ = run_oracle(w, 3)
         assert max(rel_err(Eg + Bg, Eo + Bo)) < 1e-12, n
