@@ -198,6 +198,30 @@ int mx_sources_assemble(mx_grid *g, int nsrc, int W, const int64_t *origins, con
 int mx_sources_project(mx_grid *g, int nsrc, int W, const int64_t *origins, const void *shapes,
                        void *const G[3], void *grad);
 
+/* ------------------------------------------------------------------------
+ * Batched stepping of independent 2D periodic grids (each its own size,
+ * dt and coefficients; TE+TM; no current; one fixed m >= 1 for all grids;
+ * one dtype).  Every phase of a step of all grids is one launch over the
+ * concatenated work items of the batch; with persistent = 1 all nsteps
+ * steps of all grids run inside a single cooperative launch, phases
+ * separated by grid-wide barriers whose wait is bounded (a time-out returns
+ * MX_EDEVICE).  mx_batch_init with sweeps_per_pass = 0 times candidate
+ * schedules on workspace scratch fields (the bound state is never touched)
+ * and keeps the fastest.  The workspace holds 15 arrays per grid.
+ * ------------------------------------------------------------------------ */
+typedef struct mx_batch mx_batch;
+
+int mx_batch_workspace_size(const mx_config *cfgs, int ngrids, size_t *bytes);
+int mx_batch_init(const mx_config *cfgs, int ngrids, void *stream, void *workspace,
+                  size_t workspace_bytes, mx_batch **out);
+int mx_batch_bind(mx_batch *b, int grid, void *const E[3], void *const B[3]);
+int mx_batch_step(mx_batch *b, int nsteps, int persistent);
+/* The schedule in use: sweeps per pass (tuned at init when the configs ask
+   for sweeps_per_pass = 0), total work items of one step, and the
+   workgroups of the persistent launch. */
+int mx_batch_get_plan(mx_batch *b, int *sweeps_per_pass, int *tiles_total, int *persistent_blocks);
+int mx_batch_destroy(mx_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

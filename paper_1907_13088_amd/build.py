@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmx.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["k2d.hip", "k2f.hip", "k2s.hip", "k2s_f32.hip", "k2s_f32d.hip", "k2s_f64.hip", "k2s_f64d.hip", "k3d.hip", "kadj.hip", "kbatch.hip", "mx_api.cpp"]
+SOURCES = ["k2d.hip", "k2f.hip", "k2s.hip", "k2s_f32.hip", "k2s_f32d.hip", "k2s_f64.hip", "k2s_f64d.hip", "k3d.hip", "kadj.hip", "kbatch_f32.hip", "kbatch_f64.hip", "mx_api.cpp", "mx_batch.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # packed FP32 VALU forms stay off: plain FP32 VALU only
@@ -39,7 +39,7 @@ def build(force: bool = True, verbose: bool = False) -> str:
     """Compile every source for gfx950 and link libmx.so (always rebuilds
     when force is set)."""
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    deps = [os.path.join(CSRC, s) for s in srcs] + [os.path.join(CSRC, h) for h in ("mx_internal.h", "k2s_impl.h", "stencil2d.h")] + [
+    deps = [os.path.join(CSRC, s) for s in srcs] + [os.path.join(CSRC, h) for h in ("mx_internal.h", "k2s_impl.h", "k2f_impl.h", "kbatch_impl.h", "stencil2d.h")] + [
                                                     os.path.join(HERE, "..", "include", "mx.h")]
     if not force and os.path.exists(OUT) and all(os.path.getmtime(OUT) >= os.path.getmtime(d) for d in deps):
         return OUT

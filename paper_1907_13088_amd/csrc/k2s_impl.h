@@ -55,21 +55,21 @@ __device__ void block_sum2(double &a, double &b, double *sh)
 // the FP64 norm of the last sweep's step
 enum : int { OM_STORE = 0, OM_LAST = 1, OM_RESID = 2 };
 
+// One work item: strip wid % nsx, chunk wid / nsx of rows [Y0, Y0 + L).
+// pidx is where the item's FP64 partial sums go (OM_RESID only).
+// LDS a tile needs: one double-buffered row of 3 components per level
+template <typename T, int K, int RX>
+constexpr size_t stream_lds_bytes() { return sizeof(T) * (size_t)K * 2 * 3 * (RX + 2); }
+
 template <typename T, int BLK, int K, bool DELTA, int RX, int OM>
-__global__ __launch_bounds__(RX) void k2_stream(Coef<T> c, SweepArgs<T> a, int flags, int L, int nsx,
-                                                int nwg)
+__device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T> &a, int flags, int L, int nsx,
+                                            int wid, int pidx, void *lds, double *sred)
 {
     constexpr bool TE = BLK & 1, TM = BLK & 2;
     constexpr int W = RX - 2 * K;
     constexpr int PAD = RX + 2;
-    __shared__ T xs[K][2][3][PAD];
-    __shared__ double sred[2 * RX / 64];
+    T(*xs)[2][3][PAD] = reinterpret_cast<T(*)[2][3][PAD]>(lds);
 
-    // consecutive chunks of a strip go to the same XCD (blockIdx round-robins over 8)
-    const int b = blockIdx.x;
-    const int per = (nwg + 7) / 8;
-    int wid = (b % 8) * per + b / 8;
-    if (nwg % 8 != 0 || wid >= nwg) wid = b;
     const int sx = wid % nsx, sy = wid / nsx;
 
     const int nx = c.nx, ny = c.ny;
@@ -250,10 +250,29 @@ __global__ __launch_bounds__(RX) void k2_stream(Coef<T> c, SweepArgs<T> a, int f
     if (resid) {
         block_sum2<RX>(rte, rtm, sred);
         if (threadIdx.x == 0) {
-            a.partial[2 * b] = rte;
-            a.partial[2 * b + 1] = rtm;
+            a.partial[2 * pidx] = rte;
+            a.partial[2 * pidx + 1] = rtm;
         }
     }
+    __syncthreads();   // the LDS rows are reused by the caller's next item
+}
+
+// work item of a single-grid launch: consecutive chunks of a strip go to the
+// same XCD (workgroups are dealt round-robin over the 8 XCDs)
+__device__ __forceinline__ int xcd_item(int nwg)
+{
+    const int b = blockIdx.x;
+    const int per = (nwg + 7) / 8;
+    const int wid = (b % 8) * per + b / 8;
+    return (nwg % 8 != 0 || wid >= nwg) ? b : wid;
+}
+
+template <typename T, int BLK, int K, bool DELTA, int RX, int OM>
+__global__ __launch_bounds__(RX) void k2_stream(Coef<T> c, SweepArgs<T> a, int flags, int L, int nsx, int nwg)
+{
+    __shared__ __attribute__((aligned(16))) char lds[stream_lds_bytes<T, K, RX>()];
+    __shared__ double sred[2 * RX / 64];
+    stream_tile<T, BLK, K, DELTA, RX, OM>(c, a, flags, L, nsx, xcd_item(nwg), blockIdx.x, lds, sred);
 }
 
 constexpr int SRX = 256;

@@ -70,6 +70,11 @@ int n_arrays(const mx_config *c)
 
 }  // namespace
 
+namespace mx {
+// error reporting shared with the batch entry points
+int api_fail(int code, const char *msg) { return fail(code, "%s", msg); }
+}  // namespace mx
+
 struct mx_grid {
     mx_config cfg;
     hipStream_t stream;

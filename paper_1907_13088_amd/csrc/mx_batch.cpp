@@ -1,0 +1,372 @@
+// Host side of the batched 2D stepping entry points (mx_batch_* in mx.h):
+// validation, workspace carving, device descriptors, the grouped and the
+// persistent schedules, and the autotuner for sweeps per pass and chunk
+// length.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mx_internal.h"
+
+using namespace mx;
+
+namespace mx {
+int api_fail(int code, const char *msg);   // mx_api.cpp
+}
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+int bfail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    return api_fail(code, buf);
+}
+
+#define BCHK(expr)                                                                              \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) return bfail(MX_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// full-grid arrays per grid: dE' (3), two iterates (6), second B (3), scratch
+// fields the autotuner times on (3)
+constexpr int ARRAYS = 15;
+
+int64_t cells(const mx_config &c) { return c.n[0] * c.n[1]; }
+
+template <typename T>
+void fill_coef2(const mx_config &c, Coef<T> &k)
+{
+    const double dt = c.dt, dx = c.d[0], dy = c.d[1];
+    const double rx = dt * dt / (dx * dx), ry = dt * dt / (dy * dy), rxy = dt * dt / (dx * dy);
+    std::memset(&k, 0, sizeof(k));
+    k.nx = (int)c.n[0];
+    k.ny = (int)c.n[1];
+    k.nz = 1;
+    k.tdx = (T)(dt / dx);
+    k.tdy = (T)(dt / dy);
+    k.tdz = (T)dt;
+    k.src = (T)(c.four_pi * dt);
+    k.cxx = (T)((ry - 1.0) / 6.0);
+    k.cyy = (T)((rx - 1.0) / 6.0);
+    k.cxy = (T)(-rxy / 6.0);
+    k.czx = (T)((rx - 1.0) / 6.0);
+    k.czy = (T)((ry - 1.0) / 6.0);
+    k.czz = (T)((rx + ry - 1.0) / 36.0);
+    k.lumped = 0;
+}
+
+}  // namespace
+
+struct mx_batch {
+    int ng;
+    int dtype;
+    int m;
+    hipStream_t stream;
+    int device;
+    std::vector<mx_config> cfg;
+    std::vector<int64_t> ncell;
+    std::vector<void *> E, B;          // 3 per grid (caller's)
+    std::vector<void *> ws;            // ARRAYS per grid
+    std::vector<int> bound;
+    void *desc;                        // device GridDesc<T>[ng]
+    int *items_f, *items_s;            // device prefix sums (ng + 1)
+    unsigned *bar;                     // device barrier counters
+    int *err;                          // device error flag
+    int spp, Lf, Ls;                   // schedule
+    int nf, ns;                        // items per phase
+    int pq;                            // persistent pass size (0: none)
+    bool tuned;
+};
+
+namespace {
+
+template <typename T>
+int upload(mx_batch *b, bool scratch_fields)
+{
+    // Descriptors and item tables for the current schedule.  With
+    // scratch_fields the E and B of every grid point at workspace arrays (the
+    // autotuner's trial steps never touch the caller's state).
+    std::vector<GridDesc<T>> d(b->ng);
+    std::vector<int> itf(b->ng + 1, 0), its(b->ng + 1, 0);
+    const int wf = batch2d::front_width(), wsw = batch2d::sweep_width(b->spp);
+    for (int g = 0; g < b->ng; g++) {
+        const mx_config &c = b->cfg[g];
+        GridDesc<T> &gd = d[g];
+        std::memset(&gd, 0, sizeof(gd));
+        fill_coef2(c, gd.c);
+        T **w = (T **)&b->ws[(size_t)g * ARRAYS];
+        for (int q = 0; q < 3; q++) {
+            gd.dEp[q] = w[q];
+            gd.X[0][q] = w[3 + q];
+            gd.X[1][q] = w[6 + q];
+            gd.B[1][q] = w[9 + q];
+            if (scratch_fields) {
+                gd.E[q] = w[12 + q];
+                gd.B[0][q] = w[3 + q];   // the first iterate buffer doubles as old B
+            } else {
+                gd.E[q] = (T *)b->E[3 * g + q];
+                gd.B[0][q] = (T *)b->B[3 * g + q];
+            }
+        }
+        const int nx = (int)c.n[0], ny = (int)c.n[1];
+        gd.nsx_f = (nx + wf - 1) / wf;
+        gd.nsx_s = (nx + wsw - 1) / wsw;
+        itf[g + 1] = itf[g] + gd.nsx_f * ((ny + b->Lf - 1) / b->Lf);
+        its[g + 1] = its[g] + gd.nsx_s * ((ny + b->Ls - 1) / b->Ls);
+    }
+    b->nf = itf[b->ng];
+    b->ns = its[b->ng];
+    BCHK(hipMemcpyAsync(b->desc, d.data(), sizeof(GridDesc<T>) * b->ng, hipMemcpyHostToDevice, b->stream));
+    BCHK(hipMemcpyAsync(b->items_f, itf.data(), sizeof(int) * (b->ng + 1), hipMemcpyHostToDevice, b->stream));
+    BCHK(hipMemcpyAsync(b->items_s, its.data(), sizeof(int) * (b->ng + 1), hipMemcpyHostToDevice, b->stream));
+    BCHK(hipStreamSynchronize(b->stream));   // the host vectors go out of scope
+    return MX_OK;
+}
+
+// pass sizes of one step: npass passes, sizes as equal as possible
+void pass_sizes(int m, int k, std::vector<int> &sz)
+{
+    sz.clear();
+    const int np = (m + k - 1) / k;
+    const int q = m / np, r = m % np;
+    for (int p = 0; p < np; p++) sz.push_back(p < r ? q + 1 : q);
+}
+
+template <typename T>
+int grouped_steps(mx_batch *b, int nsteps, int bin0)
+{
+    const GridDesc<T> *d = (const GridDesc<T> *)b->desc;
+    std::vector<int> sz;
+    pass_sizes(b->m, b->spp, sz);
+    int bin = bin0;
+    for (int s = 0; s < nsteps; s++) {
+        BCHK(batch2d::launch_front<T>(d, b->ng, b->items_f, b->nf, b->Lf, bin, b->stream));
+        bin ^= 1;
+        for (size_t p = 0; p < sz.size(); p++) {
+            const bool first = p == 0, last = p + 1 == sz.size();
+            BCHK(batch2d::launch_sweep<T>(d, b->ng, b->items_s, b->ns, b->Ls, sz[p], first, last,
+                                          (int)((p + 1) & 1), (int)(p & 1), b->stream));
+        }
+    }
+    return MX_OK;
+}
+
+template <typename T>
+int persistent_steps(mx_batch *b, int nsteps, int bin0)
+{
+    const int q = b->pq;
+    const int nb = batch2d::persistent_blocks<T>(q);
+    if (q <= 0 || nb <= 0) return bfail(MX_EINVAL, "no persistent schedule for m = %d", b->m);
+    // clear the error flag with a copy (no memset node in a captured stream)
+    static const int zero = 0;
+    BCHK(hipMemcpyAsync(b->err, &zero, sizeof(int), hipMemcpyHostToDevice, b->stream));
+    BCHK(batch2d::launch_persistent<T>((const GridDesc<T> *)b->desc, b->ng, b->items_f, b->items_s, b->Lf, b->Ls,
+                                       nsteps, q, b->m / q, bin0, b->bar, b->err, nb, b->stream));
+    int h = 0;
+    BCHK(hipMemcpyAsync(&h, b->err, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+    BCHK(hipStreamSynchronize(b->stream));
+    if (h) return bfail(MX_EDEVICE, "persistent batch launch: grid barrier timed out");
+    return MX_OK;
+}
+
+template <typename T>
+int autotune(mx_batch *b)
+{
+    // time one grouped step per candidate on scratch fields
+    hipEvent_t e0, e1;
+    BCHK(hipEventCreate(&e0));
+    BCHK(hipEventCreate(&e1));
+    int best_k = 5, best_l = 64;
+    float best = 1e30f;
+    const int ks[] = {3, 4, 5, 6, 7};
+    const int ls[] = {32, 64, 128};
+    for (int k : ks)
+        for (int l : ls) {
+            b->spp = k;
+            b->Lf = b->Ls = l;
+            int rc = upload<T>(b, true);
+            if (rc) return rc;
+            rc = grouped_steps<T>(b, 1, 0);   // warm
+            if (rc) return rc;
+            BCHK(hipEventRecord(e0, b->stream));
+            rc = grouped_steps<T>(b, 2, 0);
+            if (rc) return rc;
+            BCHK(hipEventRecord(e1, b->stream));
+            BCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            BCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) { best = ms; best_k = k; best_l = l; }
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    b->spp = best_k;
+    b->Lf = b->Ls = best_l;
+    return MX_OK;
+}
+
+// largest pass size in [1, 6] dividing m, closest to the tuned one
+int persistent_q(int m, int k)
+{
+    int q = 0;
+    for (int c = 1; c <= 6; c++)
+        if (m % c == 0 && (q == 0 || std::abs(c - k) <= std::abs(q - k))) q = c;
+    return q;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mx_batch_workspace_size(const mx_config *cfgs, int ngrids, size_t *bytes)
+{
+    if (!cfgs || !bytes || ngrids < 1) return bfail(MX_EINVAL, "bad batch arguments");
+    size_t tot = 0;
+    for (int g = 0; g < ngrids; g++) {
+        const mx_config &c = cfgs[g];
+        int rc = mx_validate(&c, nullptr);
+        if (rc) return rc;
+        if (c.ndim != 2 || c.blocks != MX_ALL || c.tol != 0.0 || c.lumped || c.sweeps < 1 || c.dtype != cfgs[0].dtype
+            || c.sweeps != cfgs[0].sweeps)
+            return bfail(MX_EINVAL, "grid %d: a batch holds 2D TE+TM grids of one dtype, one fixed m >= 1, "
+                                    "no lumping", g);
+        tot += ARRAYS * up((size_t)cells(c) * (c.dtype == MX_F64 ? 8 : 4));
+    }
+    const size_t dsz = cfgs[0].dtype == MX_F64 ? sizeof(GridDesc<double>) : sizeof(GridDesc<float>);
+    tot += up(dsz * ngrids) + 2 * up(sizeof(int) * (ngrids + 1)) + up(4 * sizeof(unsigned)) + up(sizeof(int));
+    *bytes = tot;
+    return MX_OK;
+}
+
+int mx_batch_init(const mx_config *cfgs, int ngrids, void *stream, void *workspace, size_t workspace_bytes,
+                  mx_batch **out)
+{
+    if (!out) return bfail(MX_EINVAL, "out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    int rc = mx_batch_workspace_size(cfgs, ngrids, &need);
+    if (rc) return rc;
+    if (!workspace || workspace_bytes < need)
+        return bfail(MX_EWORKSPACE, "batch workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, need);
+    if (((uintptr_t)workspace) % ALIGN) return bfail(MX_EINVAL, "workspace must be %zu-byte aligned", ALIGN);
+    hipPointerAttribute_t attr;
+    BCHK(hipPointerGetAttributes(&attr, workspace));
+    if (attr.type != hipMemoryTypeDevice) return bfail(MX_EINVAL, "workspace is not device memory");
+    BCHK(hipSetDevice(attr.device));
+    mx_batch *b = new mx_batch();
+    b->ng = ngrids;
+    b->dtype = cfgs[0].dtype;
+    b->m = cfgs[0].sweeps;
+    b->stream = (hipStream_t)stream;
+    b->device = attr.device;
+    b->cfg.assign(cfgs, cfgs + ngrids);
+    b->E.assign(3 * ngrids, nullptr);
+    b->B.assign(3 * ngrids, nullptr);
+    b->bound.assign(ngrids, 0);
+    char *p = (char *)workspace;
+    const size_t el = b->dtype == MX_F64 ? 8 : 4;
+    for (int g = 0; g < ngrids; g++) {
+        b->ncell.push_back(cells(cfgs[g]));
+        const size_t arr = up((size_t)b->ncell[g] * el);
+        for (int a = 0; a < ARRAYS; a++) { b->ws.push_back(p); p += arr; }
+    }
+    // zero the field arrays so trial steps never see stale bit patterns
+    const size_t field_bytes = (size_t)(p - (char *)workspace);
+    BCHK(hipMemsetAsync(workspace, 0, field_bytes, b->stream));
+    const size_t dsz = b->dtype == MX_F64 ? sizeof(GridDesc<double>) : sizeof(GridDesc<float>);
+    b->desc = p; p += up(dsz * ngrids);
+    b->items_f = (int *)p; p += up(sizeof(int) * (ngrids + 1));
+    b->items_s = (int *)p; p += up(sizeof(int) * (ngrids + 1));
+    b->bar = (unsigned *)p; p += up(4 * sizeof(unsigned));
+    b->err = (int *)p;
+    BCHK(hipMemsetAsync(b->bar, 0, 4 * sizeof(unsigned), b->stream));
+    b->spp = cfgs[0].sweeps_per_pass > 0 ? cfgs[0].sweeps_per_pass : 5;
+    b->Lf = b->Ls = 64;
+    b->tuned = false;
+    if (cfgs[0].sweeps_per_pass == 0) {
+        rc = b->dtype == MX_F64 ? autotune<double>(b) : autotune<float>(b);
+        if (rc) { delete b; return rc; }
+        b->tuned = true;
+    }
+    b->pq = persistent_q(b->m, b->spp);
+    *out = b;
+    return MX_OK;
+}
+
+int mx_batch_bind(mx_batch *b, int grid, void *const E[3], void *const B[3])
+{
+    if (!b || !E || !B || grid < 0 || grid >= b->ng) return bfail(MX_EINVAL, "bad batch bind arguments");
+    for (int q = 0; q < 3; q++) {
+        if (!E[q] || !B[q]) return bfail(MX_EINVAL, "field component %d of grid %d is NULL", q, grid);
+        b->E[3 * grid + q] = E[q];
+        b->B[3 * grid + q] = B[q];
+    }
+    b->bound[grid] = 1;
+    return MX_OK;
+}
+
+int mx_batch_step(mx_batch *b, int nsteps, int persistent)
+{
+    if (!b) return bfail(MX_EINVAL, "batch is NULL");
+    if (nsteps < 0) return bfail(MX_EINVAL, "nsteps must be >= 0");
+    for (int g = 0; g < b->ng; g++)
+        if (!b->bound[g]) return bfail(MX_ESTATE, "grid %d of the batch is not bound", g);
+    if (nsteps == 0) return MX_OK;
+    BCHK(hipSetDevice(b->device));
+    const bool f64 = b->dtype == MX_F64;
+    int rc = f64 ? upload<double>(b, false) : upload<float>(b, false);
+    if (rc) return rc;
+    if (persistent) {
+        // persistent passes all have q sweeps: swap in the item table for q
+        const int keep = b->spp;
+        b->spp = b->pq;
+        rc = f64 ? upload<double>(b, false) : upload<float>(b, false);
+        if (!rc) rc = f64 ? persistent_steps<double>(b, nsteps, 0) : persistent_steps<float>(b, nsteps, 0);
+        b->spp = keep;
+    } else {
+        rc = f64 ? grouped_steps<double>(b, nsteps, 0) : grouped_steps<float>(b, nsteps, 0);
+    }
+    if (rc) return rc;
+    // after an odd number of steps B lives in the workspace: hand it back
+    if (nsteps % 2 == 1) {
+        for (int g = 0; g < b->ng; g++)
+            for (int q = 0; q < 3; q++)
+                BCHK(hipMemcpyAsync(b->B[3 * g + q], b->ws[(size_t)g * ARRAYS + 9 + q], b->ncell[g] * (f64 ? 8 : 4),
+                                    hipMemcpyDeviceToDevice, b->stream));
+    }
+    return MX_OK;
+}
+
+int mx_batch_get_plan(mx_batch *b, int *sweeps_per_pass, int *tiles_total, int *persistent_blocks)
+{
+    if (!b) return bfail(MX_EINVAL, "batch is NULL");
+    if (sweeps_per_pass) *sweeps_per_pass = b->spp;
+    if (tiles_total) {
+        int rc = b->dtype == MX_F64 ? upload<double>(b, true) : upload<float>(b, true);
+        if (rc) return rc;
+        *tiles_total = b->nf + b->ns;
+    }
+    if (persistent_blocks)
+        *persistent_blocks = b->dtype == MX_F64 ? batch2d::persistent_blocks<double>(b->pq)
+                                                : batch2d::persistent_blocks<float>(b->pq);
+    return MX_OK;
+}
+
+int mx_batch_destroy(mx_batch *b)
+{
+    delete b;
+    return MX_OK;
+}
+
+}  // extern "C"

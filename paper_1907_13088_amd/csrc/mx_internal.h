@@ -56,6 +56,35 @@ struct FrontArgs {
     double *partial;      // per-workgroup ||dE'||^2 partials [nblocks][2], or null
 };
 
+// One grid of a batch (device-resident descriptor)
+template <typename T>
+struct GridDesc {
+    Coef<T> c;
+    T *E[3];
+    T *B[2][3];       // [0] the caller's buffers, [1] workspace (B ping-pongs per step)
+    T *dEp[3];
+    T *X[2][3];
+    int nsx_f, nsx_s; // strips of the front and of the sweep pass
+};
+
+namespace batch2d {
+constexpr int STRIP = 256;                                    // threads (columns) per strip
+inline int front_width() { return STRIP - 1 - 2; }            // no current: halo 1 left, 2 right
+inline int sweep_width(int k) { return STRIP - 2 * k; }
+template <typename T>
+hipError_t launch_front(const GridDesc<T> *d, int ng, const int *items, int nitems, int L, int bin, hipStream_t s);
+template <typename T>
+hipError_t launch_sweep(const GridDesc<T> *d, int ng, const int *items, int nitems, int L, int k, bool first,
+                        bool last, int xin, int xout, hipStream_t s);
+// co-resident workgroups of the persistent kernel for pass size q (0: unsupported q)
+template <typename T>
+int persistent_blocks(int q);
+template <typename T>
+hipError_t launch_persistent(const GridDesc<T> *d, int ng, const int *items_f, const int *items_s, int Lf, int Ls,
+                             int nsteps, int q, int npass, int bin0, unsigned *bar, int *err, int nblocks,
+                             hipStream_t s);
+}  // namespace batch2d
+
 // 2D launchers (k2d.hip)
 template <typename T>
 hipError_t launch_front_stream2d(const Coef<T> &c, int blocks, int filter_passes, const FrontArgs<T> &a,

@@ -100,6 +100,21 @@ def draw_modes(rng: np.random.Generator, N: Sequence[int], count: int, kmax: flo
     """`count` distinct lattice wavevectors with 0 < |k| <= kmax (k = 2 pi n / N)."""
     nd = len(N)
     lim = [int(math.floor(kmax * N[a] / (2 * math.pi))) for a in range(nd)]
+    ncand = 1
+    for a in range(nd):
+        ncand *= 2 * lim[a] + 1
+    if ncand <= 64 * max(count, 1):
+        # small lattice: enumerate the admissible wavevectors (one of each
+        # mirror pair) and draw without replacement; fewer than `count` may exist
+        cand = []
+        for n in np.ndindex(*[2 * lim[a] + 1 for a in range(nd)]):
+            v = tuple(int(n[a]) - lim[a] for a in range(nd))
+            k2 = sum((2 * math.pi * v[a] / N[a]) ** 2 for a in range(nd))
+            if k2 == 0.0 or k2 > kmax * kmax or tuple(-x for x in v) in cand:
+                continue
+            cand.append(v)
+        pick = rng.permutation(len(cand))[:count]
+        return [Mode(n=cand[j], amp=float(rng.normal()), phase=float(rng.uniform(0, 2 * math.pi))) for j in pick]
     seen = set()
     out: List[Mode] = []
     while len(out) < count:

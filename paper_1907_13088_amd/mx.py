@@ -65,6 +65,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
                                "(run python -m paper_1907_13088_amd.build)")
+        # torch ships its own HIP runtime under the same soname; loading torch
+        # first makes libmx bind to that one, so the process holds a single
+        # runtime (tensors allocated by torch are then known to libmx)
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp = C.c_void_p
         P = C.POINTER

@@ -1,0 +1,116 @@
+"""Batched stepping of independent grids (mx_batch_*): each grid against the
+FP64 oracle, and grouped, persistent and single-grid schedules against one
+another (the per-cell arithmetic does not depend on the schedule, so they
+agree bitwise)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1907_13088_amd import inputs as I
+from paper_1907_13088_amd import mx
+
+from gpu_helpers import log, rel_err, run_gpu, run_oracle, torch_fields, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(ws, dtype, spp=0):
+    cfgs = [mx.make_config(2, w.shape[::-1], w.dt, (1.0, 1.0), dtype, mx.MX_ALL, w.sweeps, 0.0, 0,
+                           sweeps_per_pass=spp) for w in ws]
+    b = mx.Batch(cfgs)
+    fields = []
+    for g, w in enumerate(ws):
+        E, B = torch_fields(w.E, dtype), torch_fields(w.B, dtype)
+        b.bind(g, E, B)
+        fields.append((E, B))
+    return b, fields
+
+
+def _small_set(dtype, seed=4100):
+    rng = np.random.default_rng(seed)
+    shapes = [(48, 64), (37, 100), (128, 256), (200, 33), (90, 90), (7, 5)]
+    out = []
+    for k, (ny, nx) in enumerate(shapes):
+        c = float(rng.uniform(0.3, 0.7))
+        out.append(I.modes_2d((nx, ny), courant=c, nmodes=12, npulses=0, m=20, steps=20, seed=seed + k,
+                              dtype=dtype))
+    return out
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batch_fp64_matches_oracle(persistent):
+    ws = _small_set("f64")
+    nsteps = 7
+    b, fields = _batch(ws, "f64")
+    b.step(nsteps, persistent=persistent)
+    import torch
+    torch.cuda.synchronize()
+    log(f"batch plan {b.plan()}")
+    for w, (E, B) in zip(ws, fields):
+        Eo, Bo, _ = run_oracle(w, nsteps, sweeps=20, tol=0.0)
+        e = rel_err(to_np(E + B), Eo + Bo)
+        assert max(e) < 1e-12, (w.shape, e)
+
+
+def test_batch_schedules_agree_bitwise_fp32():
+    import torch
+    ws = _small_set("f32", seed=4200)
+    res = {}
+    for name, spp, pers, nsteps in (("grouped5", 5, False, 6), ("grouped7", 7, False, 6),
+                                    ("persistent", 5, True, 6), ("tuned", 0, False, 6)):
+        b, fields = _batch(ws, "f32", spp)
+        b.step(nsteps, persistent=pers)
+        torch.cuda.synchronize()
+        res[name] = [to_np(E + B) for E, B in fields]
+        b.close()
+    for g, w in enumerate(ws):
+        Eg, Bg, _, _ = run_gpu(w, 6, tol=0.0, sweeps=20)
+        single = Eg + Bg
+        for name, out in res.items():
+            for a, s in zip(out[g], single):
+                assert np.array_equal(a, s), (name, g)
+
+
+def test_batch_step_split_equals_one_call():
+    """3 + 4 steps (odd count: B returns from the workspace) equal 7 steps."""
+    import torch
+    ws = _small_set("f32", seed=4300)
+    b1, f1 = _batch(ws, "f32", 5)
+    b1.step(7)
+    b2, f2 = _batch(ws, "f32", 5)
+    b2.step(3, persistent=True)
+    b2.step(4)
+    torch.cuda.synchronize()
+    for (E1, B1), (E2, B2) in zip(f1, f2):
+        for x, y in zip(E1 + B1, E2 + B2):
+            assert torch.equal(x, y)
+
+
+def test_batch_full_workload():
+    """64 grids with sizes drawn from {256,...,2048} per axis and Courant in
+    [0.3, 0.7], FP32, m = 20, 500 steps in one persistent launch: equal to
+    the grouped schedule bitwise, and the two smallest grids within 1e-5 of
+    the FP64 oracle after all 500 steps."""
+    import torch
+    ws = I.batch_2d()
+    ncell = sum(w.cells for w in ws)
+    log(f"batch of {len(ws)} grids, {ncell / 1e6:.1f} M cells")
+    b1, f1 = _batch(ws, "f32")
+    plan = b1.plan()
+    log(f"plan {plan}")
+    b1.step(500, persistent=True)
+    b2, f2 = _batch(ws, "f32", plan["sweeps_per_pass"])
+    b2.step(500, persistent=False)
+    torch.cuda.synchronize()
+    for (E1, B1), (E2, B2) in zip(f1, f2):
+        for x, y in zip(E1 + B1, E2 + B2):
+            assert torch.equal(x, y)
+    order = np.argsort([w.cells for w in ws])[:2]
+    for g in order:
+        w = ws[g]
+        Eo, Bo, _ = run_oracle(w, 500, sweeps=20, tol=0.0)
+        E, B = f1[g]
+        e = rel_err(to_np(E + B), Eo + Bo)
+        log(f"grid {g} {w.shape}: fp32 error after 500 steps {max(e):.2e}")
+        assert max(e) < 1e-5
