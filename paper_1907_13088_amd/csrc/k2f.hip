@@ -7,8 +7,8 @@ using namespace front2d;
 
 constexpr int FRX = 256;
 
-template <typename T, int BLK, int P>
-hipError_t front_p(const Coef<T> &c, const FrontArgs<T> &a, const T *const Bin[3], hipStream_t s, int *nwg)
+template <typename T, int BLK, int P, bool HASJ>
+hipError_t front_j(const Coef<T> &c, const FrontArgs<T> &a, const T *const Bin[3], hipStream_t s, int *nwg)
 {
     constexpr int HL = P > 1 ? P : 1, HR = P > 2 ? P : 2;
     constexpr int W = FRX - HL - HR;
@@ -16,7 +16,7 @@ hipError_t front_p(const Coef<T> &c, const FrontArgs<T> &a, const T *const Bin[3
     if (slots < 0) {
         int o = 0, dev = 0, cu = 0;
         (void)hipGetDevice(&dev);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k2_front_stream<T, BLK, P, FRX>, FRX, 0) != hipSuccess || o < 1) o = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k2_front_stream<T, BLK, P, FRX, HASJ>, FRX, 0) != hipSuccess || o < 1) o = 1;
         if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu < 1) cu = 256;
         slots = std::min(o, 4) * cu;
     }
@@ -28,9 +28,16 @@ hipError_t front_p(const Coef<T> &c, const FrontArgs<T> &a, const T *const Bin[3
     nsy = (c.ny + L - 1) / L;
     const int n = nsx * nsy;
     *nwg = n;
-    hipLaunchKernelGGL((k2_front_stream<T, BLK, P, FRX>), dim3(n), dim3(FRX), 0, s, c, a, Bin[0], Bin[1], Bin[2],
+    hipLaunchKernelGGL((k2_front_stream<T, BLK, P, FRX, HASJ>), dim3(n), dim3(FRX), 0, s, c, a, Bin[0], Bin[1], Bin[2],
                        L, nsx, n);
     return hipGetLastError();
+}
+
+template <typename T, int BLK, int P>
+hipError_t front_p(const Coef<T> &c, const FrontArgs<T> &a, const T *const Bin[3], hipStream_t s, int *nwg)
+{
+    if (a.J0[0] != nullptr) return front_j<T, BLK, P, true>(c, a, Bin, s, nwg);
+    return front_j<T, BLK, P, false>(c, a, Bin, s, nwg);
 }
 
 template <typename T, int BLK>

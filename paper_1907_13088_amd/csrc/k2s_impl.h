@@ -96,34 +96,45 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
             if (q < 2) wley[l][q] = wh[l][q] = wey[l][q] = T(0);
         }
 
-    T px[3] = {T(0), T(0), T(0)}, pc[3] = {T(0), T(0), T(0)}, pe[3] = {T(0), T(0), T(0)};
-    auto load_row = [&](int row) {
-        const size_t o = (size_t)wrapi(row, ny) * nx + gx;
+    // rows are prefetched two steps ahead into two register sets (by parity)
+    T px[2][3], pc[2][3], pe[2][3];
+#pragma unroll
+    for (int u = 0; u < 2; u++)
+#pragma unroll
+        for (int q = 0; q < 3; q++) px[u][q] = pc[u][q] = pe[u][q] = T(0);
+    // uniform bases of the level-0 iterate and of the carried quantity (on the
+    // first pass both are dE': the second read of a row hits the cache)
+    const T *xb[3], *cb[3];
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+        xb[q] = first ? a.rhs[q] : a.x_in[q];
+        cb[q] = (DELTA && !first) ? a.s_in[q] : a.rhs[q];
+    }
+    auto load_row = [&](int row, T(&x)[3], T(&cc)[3]) {
+        const unsigned o = (unsigned)(wrapi(row, ny) * nx + gx) * (unsigned)sizeof(T);
 #pragma unroll
         for (int q = 0; q < 3; q++) {
             if ((q < 2 && !TE) || (q == 2 && !TM)) continue;
-            if (first) {
-                const T v = a.rhs[q][o];
-                px[q] = v;
-                pc[q] = v;
-            } else {
-                px[q] = a.x_in[q][o];
-                pc[q] = DELTA ? a.s_in[q][o] : a.rhs[q][o];
-            }
+            x[q] = ld_off(xb[q], o);
+            cc[q] = ld_off(cb[q], o);
         }
     };
-    auto load_e = [&](int row) {
+    auto load_e = [&](int row, T(&e)[3]) {
         if (!(last && outcol && row >= Y0 && row < Y0 + L && row < ny)) return;
-        const size_t o = (size_t)row * nx + gxi;
+        const unsigned o = (unsigned)(row * nx + gxi) * (unsigned)sizeof(T);
 #pragma unroll
         for (int q = 0; q < 3; q++) {
             if ((q < 2 && !TE) || (q == 2 && !TM)) continue;
-            pe[q] = a.E[q][o];
+            e[q] = ld_off(a.E[q], o);
         }
     };
 
     const int tbeg = Y0 - K, tend = Y0 + L + 2 * K;
-    load_row(tbeg);
+    // E row r is added at step r + 2K (parity of r), x row t at step t
+    load_row(tbeg, px[tbeg & 1], pc[tbeg & 1]);
+    load_row(tbeg + 1, px[(tbeg + 1) & 1], pc[(tbeg + 1) & 1]);
+    load_e(tbeg - 2 * K, pe[tbeg & 1]);
+    load_e(tbeg + 1 - 2 * K, pe[(tbeg + 1) & 1]);
     double rte = 0.0, rtm = 0.0;
 
     // One time step.  ALL: every level receives and computes (the steady
@@ -192,7 +203,7 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
                         xs[l][pw][q][i + 1] = nv[q];
                     }
                 } else if (outcol && r >= Y0 && r < ny) {
-                    const size_t o = (size_t)r * nx + gxi;
+                    const unsigned o = (unsigned)(r * nx + gxi) * (unsigned)sizeof(T);
                     if (resid) {
                         if (TE) {
                             const double d0 = DELTA ? (double)nv[0] : (double)nv[0] - (double)wex[l][1];
@@ -208,10 +219,10 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
                     for (int q = 0; q < 3; q++) {
                         if ((q < 2 && !TE) || (q == 2 && !TM)) continue;
                         if (store) {
-                            a.x_out[q][o] = nv[q];
-                            if (DELTA) a.s_out[q][o] = nc[q];
+                            st_off(a.x_out[q], o, nv[q]);
+                            if (DELTA) st_off(a.s_out[q], o, nc[q]);
                         }
-                        if (last) a.E[q][o] = pe[q] + (DELTA ? nc[q] : nv[q]);
+                        if (last) st_off(a.E[q], o, pe[pw][q] + (DELTA ? nc[q] : nv[q]));
                     }
                 }
             }
@@ -221,14 +232,16 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
 #pragma unroll
             for (int q = 0; q < 3; q++) {
                 if ((q < 2 && !TE) || (q == 2 && !TM)) continue;
-                out[0][q] = px[q];
-                wc[0][0][q] = pc[q];
-                xs[0][pw][q][i + 1] = px[q];
+                out[0][q] = px[pw][q];
+                wc[0][0][q] = pc[pw][q];
+                xs[0][pw][q][i + 1] = px[pw][q];
             }
-            if (t + 1 < Y0 + L + K) load_row(t + 1);
+            // the freed set receives row t+2 (in the unrolled body
+            // unconditionally: a row past the end is a valid, unused row)
+            if (ALL || t + 2 < Y0 + L + K) load_row(t + 2, px[pw], pc[pw]);
         }
-        load_e(t + 1 - 2 * K);
-        __syncthreads();
+        load_e(t + 2 - 2 * K, pe[pw]);
+        lds_barrier();
     };
 
     // fill, steady state (every level active), drain
@@ -254,7 +267,7 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
             a.partial[2 * pidx + 1] = rtm;
         }
     }
-    __syncthreads();   // the LDS rows are reused by the caller's next item
+    lds_barrier();   // the LDS rows are reused by the caller's next item
 }
 
 // work item of a single-grid launch: consecutive chunks of a strip go to the

@@ -47,7 +47,7 @@ __device__ __forceinline__ void front_item(const GridDesc<T> *d, int ng, const i
     }
     fa.env_src = T(0);
     fa.partial = nullptr;
-    front2d::front_tile<T, 3, 0, RX>(gd.c, fa, gd.B[bin][0], gd.B[bin][1], gd.B[bin][2], L, gd.nsx_f,
+    front2d::front_tile<T, 3, 0, RX, false>(gd.c, fa, gd.B[bin][0], gd.B[bin][1], gd.B[bin][2], L, gd.nsx_f,
                                      it - items[g], 0, lds, sred);
 }
 

@@ -56,6 +56,30 @@ struct FrontArgs {
     double *partial;      // per-workgroup ||dE'||^2 partials [nblocks][2], or null
 };
 
+// Workgroup barrier that orders LDS only: the streaming kernels exchange rows
+// through LDS, never through global memory, so outstanding global loads (row
+// prefetches) and stores may stay in flight across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Element access by a 32-bit byte offset from a uniform base: lets the
+// compiler use the scalar-base + vector-offset addressing form, one offset
+// register shared by every component of a row.  Arrays are below 4 GiB.
+template <typename T>
+__device__ __forceinline__ T ld_off(const T *base, unsigned byte_off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void st_off(T *base, unsigned byte_off, T v)
+{
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
+}
+
 // One grid of a batch (device-resident descriptor)
 template <typename T>
 struct GridDesc {
