@@ -39,6 +39,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--spp", type=int, default=0, help="sweeps per pass (0 = library choice)")
+    ap.add_argument("--variant", type=int, default=0,
+                    help="2D sweep kernel: 0 library choice, 1 LDS tile, 2 row streaming, "
+                         "3 row streaming per block")
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true")
@@ -86,7 +89,7 @@ def main():
     def make(dtype):
         td = torch.float64 if dtype == "f64" else torch.float32
         cfg = mx.make_config(2, (n, n), w.dt, (1.0, 1.0), dtype, mx.MX_ALL, w.sweeps, 0.0,
-                             w.filter_passes, sweeps_per_pass=args.spp)
+                             w.filter_passes, sweeps_per_pass=args.spp, variant=args.variant)
         g = mx.Grid(cfg)
         E = [torch.tensor(a, dtype=td, device="cuda") for a in w.E]
         B = [torch.tensor(a, dtype=td, device="cuda") for a in w.B]

@@ -14,7 +14,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmx.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["k2d.hip", "k2f.hip", "k2s.hip", "k2s_f32.hip", "k2s_f32d.hip", "k2s_f64.hip", "k2s_f64d.hip", "k3d.hip", "kadj.hip", "kbatch_f32.hip", "kbatch_f64.hip", "mx_api.cpp", "mx_batch.cpp"]
+# the long compile units first, so that the parallel build finishes early
+SOURCES = ["k2s_f32_tm.hip", "k2s_f32d_tm.hip", "k2s_f32_te.hip", "k2s_f32d_te.hip", "k2s_f32_all.hip",
+           "k2s_f32d_all.hip", "k2s_f64_tm.hip", "k2s_f64d_tm.hip", "k2s_f64_te.hip", "k2s_f64d_te.hip",
+           "k2s_f64_all.hip", "k2s_f64d_all.hip", "k2d.hip", "k2f.hip", "kbatch_f32.hip", "kbatch_f64.hip",
+           "k3d.hip", "kadj.hip", "k2s.hip", "mx_api.cpp", "mx_batch.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # packed FP32 VALU forms stay off: plain FP32 VALU only

@@ -105,14 +105,16 @@ __global__ __launch_bounds__(NT) void k2_sweep(Coef<T> c, SweepArgs<T> a, int fl
             const bool interior = cx >= K && cx < K + TX && cy >= K && cy < K + TY;
             if (TE) {
                 const T *X = src, *Y = src + NR;
-                const T ax = a_te_x(c.cxx, c.cxy, d2(X[cc - RX], X[cc], X[cc + RX]),
-                                    (Y[cc + 1] - Y[cc]) - (Y[cc + 1 - RX] - Y[cc - RX]));
-                const T ay = a_te_y(c.cyy, c.cxy, d2(Y[cc - 1], Y[cc], Y[cc + 1]),
-                                    (X[cc + RX] - X[cc + RX - 1]) - (X[cc] - X[cc - 1]));
+                const T lyy = d2(X[cc - RX], X[cc], X[cc + RX]);
+                const T dg = (Y[cc + 1] - Y[cc]) - (Y[cc + 1 - RX] - Y[cc - RX]);
+                const T lxx = d2(Y[cc - 1], Y[cc], Y[cc + 1]);
+                const T dh = (X[cc + RX] - X[cc + RX - 1]) - (X[cc] - X[cc - 1]);
                 if (!DELTA) {
-                    dst[cc] = own[s][0] + ax;
-                    dst[NR + cc] = own[s][1] + ay;
+                    dst[cc] = a_te_x_b(c.cxx, c.cxy, lyy, dg, own[s][0]);
+                    dst[NR + cc] = a_te_y_b(c.cyy, c.cxy, lxx, dh, own[s][1]);
                 } else {
+                    const T ax = a_te_x(c.cxx, c.cxy, lyy, dg);
+                    const T ay = a_te_y(c.cyy, c.cxy, lxx, dh);
                     dst[cc] = ax;
                     dst[NR + cc] = ay;
                     if (interior) { own[s][0] += ax; own[s][1] += ay; }
@@ -125,10 +127,10 @@ __global__ __launch_bounds__(NT) void k2_sweep(Coef<T> c, SweepArgs<T> a, int fl
                 const T lxp = d2(Z[cc + RX - 1], Z[cc + RX], Z[cc + RX + 1]);
                 const T lxm = d2(Z[cc - RX - 1], Z[cc - RX], Z[cc - RX + 1]);
                 const T ly0 = d2(Z[cc - RX], Z[cc], Z[cc + RX]);
-                const T az = a_tm(c.czx, c.czy, c.czz, lx0, ly0, d2(lxm, lx0, lxp));
                 if (!DELTA) {
-                    dst[qz * NR + cc] = own[s][qz] + az;
+                    dst[qz * NR + cc] = a_tm_b(c.czx, c.czy, c.czz, lx0, ly0, d2(lxm, lx0, lxp), own[s][qz]);
                 } else {
+                    const T az = a_tm(c.czx, c.czy, c.czz, lx0, ly0, d2(lxm, lx0, lxp));
                     dst[qz * NR + cc] = az;
                     if (interior) own[s][qz] += az;
                 }

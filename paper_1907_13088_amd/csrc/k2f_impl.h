@@ -120,8 +120,15 @@ __device__ __forceinline__ void front_tile(const Coef<T> &c, const FrontArgs<T> 
 #pragma unroll
         for (int q = 0; q < 3; q++) fy[k][q][0] = fy[k][q][1] = T(0);
 
-    auto load = [&](int t, T(&e)[3], T(&bb)[3], T(&j)[3]) {
-        const unsigned oe = (unsigned)(wrapi(t, ny) * nx + gx) * (unsigned)sizeof(T);
+    // rows are loaded in order, one per step: byte offsets of the next E/B
+    // row and of the next current row advance with a wrap (uniform scalars)
+    const int tb = std::min(Y0 - 1, Y0 - 2 * P + 2), te = Y0 + L + 3;
+    const unsigned rowb = (unsigned)nx * (unsigned)sizeof(T);
+    const unsigned allb = rowb * (unsigned)ny;
+    const unsigned colb = (unsigned)gx * (unsigned)sizeof(T);
+    unsigned loe = (unsigned)wrapi(tb, ny) * rowb, loj = (unsigned)wrapi(tb + D, ny) * rowb;
+    auto load = [&](T(&e)[3], T(&bb)[3], T(&j)[3]) {
+        const unsigned oe = loe + colb;
 #pragma unroll
         for (int q = 0; q < 3; q++) {
             if ((q < 2 && !TE) || (q == 2 && !TM)) continue;
@@ -129,19 +136,22 @@ __device__ __forceinline__ void front_tile(const Coef<T> &c, const FrontArgs<T> 
         }
         if (TM) { bb[0] = ld_off(Bin0, oe); bb[1] = ld_off(Bin1, oe); }
         if (TE) bb[2] = ld_off(Bin2, oe);
+        loe += rowb;
+        if (loe >= allb) loe -= allb;
         if constexpr (hasj) {
-            const unsigned oj = (unsigned)(wrapi(t + D, ny) * nx + gx) * (unsigned)sizeof(T);
+            const unsigned oj = loj + colb;
 #pragma unroll
             for (int q = 0; q < 3; q++) {
                 if ((q < 2 && !TE) || (q == 2 && !TM)) continue;
                 j[q] = ld_off(a.J0[q], oj);
             }
+            loj += rowb;
+            if (loj >= allb) loj -= allb;
         }
     };
 
-    const int tb = std::min(Y0 - 1, Y0 - 2 * P + 2), te = Y0 + L + 3;
-    load(tb, pE[tb & 1], pB[tb & 1], pJ[tb & 1]);
-    if (tb + 1 < te) load(tb + 1, pE[(tb + 1) & 1], pB[(tb + 1) & 1], pJ[(tb + 1) & 1]);
+    load(pE[tb & 1], pB[tb & 1], pJ[tb & 1]);
+    if (tb + 1 < te) load(pE[(tb + 1) & 1], pB[(tb + 1) & 1], pJ[(tb + 1) & 1]);
     double nte = 0.0, ntm = 0.0;
 
     auto step = [&](const int t, auto par_tag, auto all_tag) {
@@ -153,7 +163,7 @@ __device__ __forceinline__ void front_tile(const Coef<T> &c, const FrontArgs<T> 
         const T jr[3] = {pJ[pw][0], pJ[pw][1], pJ[pw][2]};
         // the freed register set receives row t+2 (in the unrolled body
         // unconditionally: a row past the end is a valid, unused row)
-        if (ALL || t + 2 < te) load(t + 2, pE[pw], pB[pw], pJ[pw]);
+        if (ALL || t + 2 < te) load(pE[pw], pB[pw], pJ[pw]);
         // B^{n+1/2} of row t-1 = B^{n-1/2} - dt curl E^n (E rows t-1 and t)
         T bp0[3] = {T(0), T(0), T(0)};
         if (TM) {

@@ -55,12 +55,27 @@ __device__ void block_sum2(double &a, double &b, double *sh)
 // the FP64 norm of the last sweep's step
 enum : int { OM_STORE = 0, OM_LAST = 1, OM_RESID = 2 };
 
+// LDS rows: TE levels hold (Ex, Ey) pairs (one 8- or 16-byte write and one
+// paired read per cell), TM levels hold Ez
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair {
+    T x, y;
+};
+
+// rows in flight per thread (prefetch depth): two rows; deeper prefetch
+// measured no faster (the passes are issue bound, not latency bound)
+template <typename T, int BLK, int K>
+constexpr int stream_pf() { return 2; }
+
+// components a block set carries (TE: Ex, Ey; TM: Ez)
+constexpr int stream_nc(int blk) { return ((blk & 1) ? 2 : 0) + ((blk & 2) ? 1 : 0); }
+
+// LDS a tile needs: one double-buffered row of each carried component per level
+template <typename T, int BLK, int K, int RX>
+constexpr size_t stream_lds_bytes() { return sizeof(T) * (size_t)K * 2 * stream_nc(BLK) * (RX + 2); }
+
 // One work item: strip wid % nsx, chunk wid / nsx of rows [Y0, Y0 + L).
 // pidx is where the item's FP64 partial sums go (OM_RESID only).
-// LDS a tile needs: one double-buffered row of 3 components per level
-template <typename T, int K, int RX>
-constexpr size_t stream_lds_bytes() { return sizeof(T) * (size_t)K * 2 * 3 * (RX + 2); }
-
 template <typename T, int BLK, int K, bool DELTA, int RX, int OM>
 __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T> &a, int flags, int L, int nsx,
                                             int wid, int pidx, void *lds, double *sred)
@@ -68,7 +83,9 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
     constexpr bool TE = BLK & 1, TM = BLK & 2;
     constexpr int W = RX - 2 * K;
     constexpr int PAD = RX + 2;
-    T(*xs)[2][3][PAD] = reinterpret_cast<T(*)[2][3][PAD]>(lds);
+    // column j of a level row sits at index j + 1 - (strip origin - K)
+    Pair<T>(*xp)[2][PAD] = reinterpret_cast<Pair<T>(*)[2][PAD]>(lds);
+    T(*xz)[2][PAD] = reinterpret_cast<T(*)[2][PAD]>((char *)lds + (TE ? sizeof(Pair<T>) * K * 2 * PAD : 0));
 
     const int sx = wid % nsx, sy = wid / nsx;
 
@@ -82,6 +99,7 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
     constexpr bool resid = OM == OM_RESID;
     constexpr bool store = OM != OM_LAST;
     const bool outcol = i >= K && i < RX - K && gxi < nx;
+    const int rend = std::min(Y0 + L, ny);   // rows this item writes: [Y0, rend)
 
     T out[K + 1][3];
     T wex[K + 1][3], wez[K + 1][3], wg[K + 1][3], wlx[K + 1][3];
@@ -96,10 +114,13 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
             if (q < 2) wley[l][q] = wh[l][q] = wey[l][q] = T(0);
         }
 
-    // rows are prefetched two steps ahead into two register sets (by parity)
-    T px[2][3], pc[2][3], pe[2][3];
+    // rows are prefetched PF steps ahead through a FIFO of PF register sets
+    // (in the unrolled steady state the shifts are register renaming)
+    constexpr int PF = stream_pf<T, BLK, K>();
+    static_assert(6 % PF == 0, "the unrolled group of 6 steps must cycle the FIFO");
+    T px[PF][3], pc[PF][3], pe[PF][3];
 #pragma unroll
-    for (int u = 0; u < 2; u++)
+    for (int u = 0; u < PF; u++)
 #pragma unroll
         for (int q = 0; q < 3; q++) px[u][q] = pc[u][q] = pe[u][q] = T(0);
     // uniform bases of the level-0 iterate and of the carried quantity (on the
@@ -110,17 +131,26 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
         xb[q] = first ? a.rhs[q] : a.x_in[q];
         cb[q] = (DELTA && !first) ? a.s_in[q] : a.rhs[q];
     }
-    auto load_row = [&](int row, T(&x)[3], T(&cc)[3]) {
-        const unsigned o = (unsigned)(wrapi(row, ny) * nx + gx) * (unsigned)sizeof(T);
+    // byte offset of the next level-0 row to load, advanced with a wrap
+    // (a uniform scalar), plus the thread's column
+    const unsigned rowb = (unsigned)nx * (unsigned)sizeof(T);
+    const unsigned allb = rowb * (unsigned)ny;
+    const unsigned colb = (unsigned)gx * (unsigned)sizeof(T);
+    const int tbeg = Y0 - K, tend = Y0 + L + 2 * K;
+    unsigned lo = (unsigned)wrapi(tbeg, ny) * rowb;
+    auto load_row = [&](T(&x)[3], T(&cc)[3]) {
+        const unsigned o = lo + colb;
 #pragma unroll
         for (int q = 0; q < 3; q++) {
             if ((q < 2 && !TE) || (q == 2 && !TM)) continue;
             x[q] = ld_off(xb[q], o);
             cc[q] = ld_off(cb[q], o);
         }
+        lo += rowb;
+        if (lo >= allb) lo -= allb;
     };
     auto load_e = [&](int row, T(&e)[3]) {
-        if (!(last && outcol && row >= Y0 && row < Y0 + L && row < ny)) return;
+        if (!(last && outcol && row >= Y0 && row < rend)) return;
         const unsigned o = (unsigned)(row * nx + gxi) * (unsigned)sizeof(T);
 #pragma unroll
         for (int q = 0; q < 3; q++) {
@@ -129,43 +159,44 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
         }
     };
 
-    const int tbeg = Y0 - K, tend = Y0 + L + 2 * K;
-    // E row r is added at step r + 2K (parity of r), x row t at step t
-    load_row(tbeg, px[tbeg & 1], pc[tbeg & 1]);
-    load_row(tbeg + 1, px[(tbeg + 1) & 1], pc[(tbeg + 1) & 1]);
-    load_e(tbeg - 2 * K, pe[tbeg & 1]);
-    load_e(tbeg + 1 - 2 * K, pe[(tbeg + 1) & 1]);
+    // x row t is consumed at step t, E row r at step r + 2K, both from the
+    // head of the FIFO
+#pragma unroll
+    for (int u = 0; u < PF; u++) {
+        load_row(px[u], pc[u]);
+        load_e(tbeg + u - 2 * K, pe[u]);
+    }
     double rte = 0.0, rtm = 0.0;
 
     // One time step.  ALL: every level receives and computes (the steady
     // state between pipeline fill and drain), so no row-range tests are needed
     // and the window shifts become register renaming once unrolled.
-    auto step = [&](const int t, auto all_tag, auto par_tag) {
+    auto step = [&](const int t, auto all_tag, auto slot_tag) {
         constexpr bool ALL = decltype(all_tag)::value;
-        // parity of t: compile time in the unrolled steady state (t even at
-        // the start of each group), so LDS slot addresses are constants there
-        const int pw = ALL ? decltype(par_tag)::value : (t & 1);
+        constexpr int SL = decltype(slot_tag)::value;   // position in the group of 6 (ALL)
+        constexpr int ps = 0;
+        // LDS row buffer of this step: compile time in the unrolled steady
+        // state, so LDS slot addresses are constants there
+        const int pw = ALL ? (SL & 1) : (t & 1);
         const int pr = pw ^ 1;
 #pragma unroll
         for (int l = K; l >= 1; l--) {
             // arrival of row t-2l+1 of level l-1 (computed at the previous step)
             const int rho = t - 2 * l + 1;
             if (ALL || (rho >= Y0 - K + (l - 1) && rho < Y0 + L + K - (l - 1))) {
-                const T *X = &xs[l - 1][pr][0][0];
-                const T *Y = &xs[l - 1][pr][1][0];
-                const T *Z = &xs[l - 1][pr][2][0];
                 if (TE) {
+                    const Pair<T> pm = xp[l - 1][pr][i];       // column - 1
+                    const Pair<T> pp = xp[l - 1][pr][i + 2];   // column + 1
                     const T exn = out[l - 1][0], eyn = out[l - 1][1];
-                    const T eyp = Y[i + 2], eym = Y[i], exm = X[i];
                     wex[l][0] = wex[l][1]; wex[l][1] = wex[l][2]; wex[l][2] = exn;
-                    wg[l][0] = wg[l][1]; wg[l][1] = wg[l][2]; wg[l][2] = eyp - eyn;
-                    wley[l][0] = wley[l][1]; wley[l][1] = d2(eym, eyn, eyp);
-                    wh[l][0] = wh[l][1]; wh[l][1] = exn - exm;
+                    wg[l][0] = wg[l][1]; wg[l][1] = wg[l][2]; wg[l][2] = pp.y - eyn;
+                    wley[l][0] = wley[l][1]; wley[l][1] = d2(pm.y, eyn, pp.y);
+                    wh[l][0] = wh[l][1]; wh[l][1] = exn - pm.x;
                     wey[l][0] = wey[l][1]; wey[l][1] = eyn;
                 }
                 if (TM) {
                     const T ezn = out[l - 1][2];
-                    const T ezp = Z[i + 2], ezm = Z[i];
+                    const T ezp = xz[l - 1][pr][i + 2], ezm = xz[l - 1][pr][i];
                     wez[l][0] = wez[l][1]; wez[l][1] = wez[l][2]; wez[l][2] = ezn;
                     wlx[l][0] = wlx[l][1]; wlx[l][1] = wlx[l][2]; wlx[l][2] = d2(ezm, ezn, ezp);
                 }
@@ -177,22 +208,30 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
             if (ALL || (r >= Y0 - K + l && r < Y0 + L + K - l)) {
                 T nv[3] = {T(0), T(0), T(0)}, nc[3] = {T(0), T(0), T(0)};
                 if (TE) {
-                    const T ax = a_te_x(c.cxx, c.cxy, d2(wex[l][0], wex[l][1], wex[l][2]), wg[l][1] - wg[l][0]);
-                    const T ay = a_te_y(c.cyy, c.cxy, wley[l][0], wh[l][1] - wh[l][0]);
+                    const T lyy = d2(wex[l][0], wex[l][1], wex[l][2]);
+                    const T dg = wg[l][1] - wg[l][0];
+                    const T dh = wh[l][1] - wh[l][0];
                     if (!DELTA) {
-                        nv[0] = wc[l][0][0] + ax; nv[1] = wc[l][0][1] + ay;
+                        nv[0] = a_te_x_b(c.cxx, c.cxy, lyy, dg, wc[l][0][0]);
+                        nv[1] = a_te_y_b(c.cyy, c.cxy, wley[l][0], dh, wc[l][0][1]);
                         nc[0] = wc[l][0][0]; nc[1] = wc[l][0][1];
                     } else {
-                        nv[0] = ax; nv[1] = ay;
-                        nc[0] = wc[l][0][0] + ax; nc[1] = wc[l][0][1] + ay;
+                        nv[0] = a_te_x(c.cxx, c.cxy, lyy, dg);
+                        nv[1] = a_te_y(c.cyy, c.cxy, wley[l][0], dh);
+                        nc[0] = wc[l][0][0] + nv[0]; nc[1] = wc[l][0][1] + nv[1];
                     }
                 }
                 if (TM) {
                     const T lx0 = wlx[l][1];
                     const T ly0 = d2(wez[l][0], wez[l][1], wez[l][2]);
-                    const T az = a_tm(c.czx, c.czy, c.czz, lx0, ly0, d2(wlx[l][0], lx0, wlx[l][2]));
-                    if (!DELTA) { nv[2] = wc[l][0][2] + az; nc[2] = wc[l][0][2]; }
-                    else { nv[2] = az; nc[2] = wc[l][0][2] + az; }
+                    const T lxy = d2(wlx[l][0], lx0, wlx[l][2]);
+                    if (!DELTA) {
+                        nv[2] = a_tm_b(c.czx, c.czy, c.czz, lx0, ly0, lxy, wc[l][0][2]);
+                        nc[2] = wc[l][0][2];
+                    } else {
+                        nv[2] = a_tm(c.czx, c.czy, c.czz, lx0, ly0, lxy);
+                        nc[2] = wc[l][0][2] + nv[2];
+                    }
                 }
                 if (l < K) {
 #pragma unroll
@@ -200,9 +239,11 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
                         if ((q < 2 && !TE) || (q == 2 && !TM)) continue;
                         out[l][q] = nv[q];
                         wc[l][0][q] = nc[q];   // carried value of this row, read by level l+1 next step
-                        xs[l][pw][q][i + 1] = nv[q];
                     }
-                } else if (outcol && r >= Y0 && r < ny) {
+                    if (TE) xp[l][pw][i + 1] = Pair<T>{nv[0], nv[1]};
+                    if (TM) xz[l][pw][i + 1] = nv[2];
+                } else if (outcol && (ALL ? r < rend : (r >= Y0 && r < rend))) {
+                    // (in the steady state r >= Y0 holds: t >= Y0 + 2K)
                     const unsigned o = (unsigned)(r * nx + gxi) * (unsigned)sizeof(T);
                     if (resid) {
                         if (TE) {
@@ -222,7 +263,7 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
                             st_off(a.x_out[q], o, nv[q]);
                             if (DELTA) st_off(a.s_out[q], o, nc[q]);
                         }
-                        if (last) st_off(a.E[q], o, pe[pw][q] + (DELTA ? nc[q] : nv[q]));
+                        if (last) st_off(a.E[q], o, pe[ps][q] + (DELTA ? nc[q] : nv[q]));
                     }
                 }
             }
@@ -232,34 +273,47 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
 #pragma unroll
             for (int q = 0; q < 3; q++) {
                 if ((q < 2 && !TE) || (q == 2 && !TM)) continue;
-                out[0][q] = px[pw][q];
-                wc[0][0][q] = pc[pw][q];
-                xs[0][pw][q][i + 1] = px[pw][q];
+                out[0][q] = px[ps][q];
+                wc[0][0][q] = pc[ps][q];
             }
-            // the freed set receives row t+2 (in the unrolled body
+            if (TE) xp[0][pw][i + 1] = Pair<T>{px[ps][0], px[ps][1]};
+            if (TM) xz[0][pw][i + 1] = px[ps][2];
+            // shift; the tail receives row t+PF (in the unrolled body
             // unconditionally: a row past the end is a valid, unused row)
-            if (ALL || t + 2 < Y0 + L + K) load_row(t + 2, px[pw], pc[pw]);
+#pragma unroll
+            for (int u = 0; u + 1 < PF; u++)
+#pragma unroll
+                for (int q = 0; q < 3; q++) { px[u][q] = px[u + 1][q]; pc[u][q] = pc[u + 1][q]; }
+            if (ALL || t + PF < Y0 + L + K) load_row(px[PF - 1], pc[PF - 1]);
         }
-        load_e(t + 2 - 2 * K, pe[pw]);
+        if (last) {
+#pragma unroll
+            for (int u = 0; u + 1 < PF; u++)
+#pragma unroll
+                for (int q = 0; q < 3; q++) pe[u][q] = pe[u + 1][q];
+            load_e(t + PF - 2 * K, pe[PF - 1]);
+        }
         lds_barrier();
     };
+    // a step outside the steady state (set index and LDS buffer at run time)
+    auto step_edge = [&](const int t) { step(t, std::false_type{}, std::integral_constant<int, 0>{}); };
 
     // fill, steady state (every level active), drain
     const int ts0 = Y0 + 2 * K, ts1 = Y0 + L + K;
     int t = tbeg;
-    using P0 = std::integral_constant<int, 0>;
-    using P1 = std::integral_constant<int, 1>;
-    for (; (t < ts0 || (t & 1)) && t < tend; t++) step(t, std::false_type{}, P0{});
-    constexpr int U = 6;   // multiple of the window periods (2 and 3) and even
-    for (; t + U <= ts1; t += U) {
-        step(t + 0, std::true_type{}, P0{});
-        step(t + 1, std::true_type{}, P1{});
-        step(t + 2, std::true_type{}, P0{});
-        step(t + 3, std::true_type{}, P1{});
-        step(t + 4, std::true_type{}, P0{});
-        step(t + 5, std::true_type{}, P1{});
+    using A = std::true_type;
+    for (; (t < ts0 || (t & 1)) && t < tend; t++) step_edge(t);
+    // groups of 6 steps: a multiple of the window periods (2 and 3), of the
+    // LDS double buffer and of the prefetch depth
+    for (; t + 6 <= ts1; t += 6) {
+        step(t + 0, A{}, std::integral_constant<int, 0>{});
+        step(t + 1, A{}, std::integral_constant<int, 1>{});
+        step(t + 2, A{}, std::integral_constant<int, 2>{});
+        step(t + 3, A{}, std::integral_constant<int, 3>{});
+        step(t + 4, A{}, std::integral_constant<int, 4>{});
+        step(t + 5, A{}, std::integral_constant<int, 5>{});
     }
-    for (; t < tend; t++) step(t, std::false_type{}, P0{});
+    for (; t < tend; t++) step_edge(t);
     if (resid) {
         block_sum2<RX>(rte, rtm, sred);
         if (threadIdx.x == 0) {
@@ -283,7 +337,7 @@ __device__ __forceinline__ int xcd_item(int nwg)
 template <typename T, int BLK, int K, bool DELTA, int RX, int OM>
 __global__ __launch_bounds__(RX) void k2_stream(Coef<T> c, SweepArgs<T> a, int flags, int L, int nsx, int nwg)
 {
-    __shared__ __attribute__((aligned(16))) char lds[stream_lds_bytes<T, K, RX>()];
+    __shared__ __attribute__((aligned(16))) char lds[stream_lds_bytes<T, BLK, K, RX>()];
     __shared__ double sred[2 * RX / 64];
     stream_tile<T, BLK, K, DELTA, RX, OM>(c, a, flags, L, nsx, xcd_item(nwg), blockIdx.x, lds, sred);
 }
@@ -328,33 +382,32 @@ hipError_t stream_k(const Coef<T> &c, int flags, const SweepArgs<T> &a, hipStrea
     return hipErrorInvalidValue;
 }
 
+// deepest pass (sweeps per pass) of a block set's kernel: the per-level
+// register windows must leave two waves per SIMD (TE carries 2 components,
+// TM one, both together 3)
 template <typename T, int BLK, bool DELTA>
-hipError_t stream_blk(const Coef<T> &c, int k, int flags, const SweepArgs<T> &a, hipStream_t s, int *nwg,
-                      int slots)
+constexpr int stream_kmax()
 {
-    switch (k) {
-    case 1: return stream_k<T, BLK, 1, DELTA>(c, flags, a, s, nwg, slots);
-    case 2: return stream_k<T, BLK, 2, DELTA>(c, flags, a, s, nwg, slots);
-    case 3: return stream_k<T, BLK, 3, DELTA>(c, flags, a, s, nwg, slots);
-    case 4: return stream_k<T, BLK, 4, DELTA>(c, flags, a, s, nwg, slots);
-    case 5: return stream_k<T, BLK, 5, DELTA>(c, flags, a, s, nwg, slots);
-    case 6: return stream_k<T, BLK, 6, DELTA>(c, flags, a, s, nwg, slots);
-    case 7: return stream_k<T, BLK, 7, DELTA>(c, flags, a, s, nwg, slots);
-    case 8: return stream_k<T, BLK, 8, DELTA>(c, flags, a, s, nwg, slots);
-    default: return hipErrorInvalidValue;
+    return sizeof(T) == 4 ? (BLK == 1 ? (DELTA ? 9 : 10) : BLK == 2 ? 16 : (DELTA ? 6 : 7)) : (BLK == 1 ? (DELTA ? 4 : 5) : BLK == 2 ? 8 : 3);
+}
+
+template <typename T, int BLK, bool DELTA, int K>
+hipError_t stream_kdisp(const Coef<T> &c, int k, int flags, const SweepArgs<T> &a, hipStream_t s, int *nwg,
+                        int slots)
+{
+    if constexpr (K == 0) {
+        return hipErrorInvalidValue;
+    } else {
+        if (k == K) return stream_k<T, BLK, K, DELTA>(c, flags, a, s, nwg, slots);
+        return stream_kdisp<T, BLK, DELTA, K - 1>(c, k, flags, a, s, nwg, slots);
     }
 }
 
-template <typename T, bool DELTA>
-hipError_t launch(const Coef<T> &c, int blocks, int k, int flags, const SweepArgs<T> &a, hipStream_t s,
-                  int *nwg, int slots)
+// one pass of k sweeps over the TE (BLK 1) or the TM (BLK 2) block, or both (3)
+template <typename T, bool DELTA, int BLK>
+hipError_t launch(const Coef<T> &c, int k, int flags, const SweepArgs<T> &a, hipStream_t s, int *nwg, int slots)
 {
-    switch (blocks) {
-    case 1: return stream_blk<T, 1, DELTA>(c, k, flags, a, s, nwg, slots);
-    case 2: return stream_blk<T, 2, DELTA>(c, k, flags, a, s, nwg, slots);
-    case 3: return stream_blk<T, 3, DELTA>(c, k, flags, a, s, nwg, slots);
-    }
-    return hipErrorInvalidValue;
+    return stream_kdisp<T, BLK, DELTA, stream_kmax<T, BLK, DELTA>()>(c, k, flags, a, s, nwg, slots);
 }
 
 }  // namespace stream2d

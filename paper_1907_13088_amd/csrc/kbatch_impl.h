@@ -83,7 +83,7 @@ template <typename T, int K, int OM>
 __global__ __launch_bounds__(RX) void kb_sweep(const GridDesc<T> *d, int ng, const int *items, int L, int first,
                                                int xin, int xout)
 {
-    __shared__ __attribute__((aligned(16))) char lds[stream2d::stream_lds_bytes<T, K, RX>()];
+    __shared__ __attribute__((aligned(16))) char lds[stream2d::stream_lds_bytes<T, 3, K, RX>()];
     __shared__ double sred[2 * RX / 64];
     sweep_item<T, K, OM>(d, ng, items, L, first != 0, xin, xout, blockIdx.x, lds, sred);
 }
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(RX) void kb_persistent(const GridDesc<T> *d, int ng
                                                     int bin0, unsigned *bar, int *err)
 {
     __shared__ __attribute__((aligned(16)))
-        char lds[cmax(front2d::front_lds_bytes<T, 0, RX>(), stream2d::stream_lds_bytes<T, Q, RX>())];
+        char lds[cmax(front2d::front_lds_bytes<T, 0, RX>(), stream2d::stream_lds_bytes<T, 3, Q, RX>())];
     __shared__ double sred[2 * RX / 64];
     __shared__ int sflag;
     const int nf = items_f[ng], ns = items_s[ng];

@@ -47,17 +47,36 @@ int64_t max_wg(const mx_config *c)
     const int64_t nx = c->n[0], ny = c->n[1], nz = c->ndim == 3 ? c->n[2] : 1;
     // 2D front tiles 64x16, 2D sweep tiles 64x8 at the smallest, 3D 64x4 per plane
     const int64_t a = ((nx + 63) / 64) * ((ny + 3) / 4) * nz;
-    // the streaming sweep launches at most one workgroup per (strip, row)
-    const int64_t b = ((nx + 239) / 240 + 1) * ny;
+    // the streaming sweep launches at most one workgroup per (strip, row);
+    // strips are at least 256 - 2 * 16 columns wide
+    const int64_t b = ((nx + 223) / 224 + 1) * ny;
     return std::max(a, b);
 }
 
-int default_spp(const mx_config *c)
+// Sweeps per pass of each 2D block (TE, TM).  The LDS-tile kernel (variant
+// 1) and the joint row-streaming kernel (variant 2) run both blocks in one
+// pass; the per-block row-streaming kernels (variant 3) run each block on
+// its own, as deep as its register windows allow.  Under a tolerance both
+// blocks use the same depth, which is then also the granularity of the
+// stopping test.
+void pass_depths(const mx_config *c, int variant, int out[2])
 {
-    if (c->ndim == 3) return 1;
-    const bool stream = c->variant != 1;
-    if (c->dtype == MX_F64) return stream ? (c->blocks == MX_ALL ? 3 : 4) : 4;
-    return stream ? 7 : 5;
+    if (c->ndim == 3) { out[0] = out[1] = 1; return; }
+    const bool f64 = c->dtype == MX_F64;
+    if (variant == 1) {
+        const int k = c->sweeps_per_pass > 0 ? c->sweeps_per_pass : (f64 ? 4 : 5);
+        out[0] = out[1] = k;
+        return;
+    }
+    const bool tolmode = c->tol > 0.0;
+    const bool delta = tolmode && c->form == MX_FORM_DELTA;
+    const bool joint = variant == 2 && c->blocks == MX_ALL;
+    const int kmax[2] = {mx::stream2d_kmax(f64, joint ? 3 : 1, delta), mx::stream2d_kmax(f64, joint ? 3 : 2, delta)};
+    for (int b = 0; b < 2; b++) {
+        int k = c->sweeps_per_pass > 0 ? c->sweeps_per_pass : kmax[b];
+        if (tolmode && c->sweeps_per_pass <= 0) k = std::min(kmax[0], kmax[1]);
+        out[b] = std::min(k, kmax[b]);
+    }
 }
 
 // number of full-grid arrays in the workspace
@@ -89,8 +108,9 @@ struct mx_grid {
     int bloc[3];          // 2D: where component q of B currently lives (0 user, 1 workspace)
     double *partial;      // device
     double *red;          // device, 2 doubles
-    int spp;
-    int variant;          // 2D sweep kernel in use: 1 LDS tile, 2 row streaming
+    int spp[2];           // sweeps per pass of the TE and TM blocks (3D: [0])
+    int variant;          // 2D sweep kernel in use: 1 LDS tile, 2 row streaming (blocks
+                          // together), 3 row streaming (each block on its own)
     Coef<float> cf;
     Coef<double> cd;
     // timing (mx_profile_*)
@@ -210,8 +230,10 @@ int mx_validate(const mx_config *c, int *warn)
     if (c->lumped != 0 && c->lumped != 1) return fail(MX_EINVAL, "lumped must be 0 or 1");
     if (!std::isfinite(c->four_pi)) return fail(MX_EINVAL, "four_pi must be finite");
     if (c->form != MX_FORM_STANDARD && c->form != MX_FORM_DELTA) return fail(MX_EINVAL, "bad form");
-    if (c->sweeps_per_pass < 0 || c->sweeps_per_pass > 8) return fail(MX_EINVAL, "sweeps_per_pass must be in [0, 8]");
-    if (c->variant < 0 || c->variant > 2) return fail(MX_EINVAL, "variant must be 0, 1 or 2");
+    if (c->sweeps_per_pass < 0 || c->sweeps_per_pass > 16) return fail(MX_EINVAL, "sweeps_per_pass must be in [0, 16]");
+    if (c->variant < 0 || c->variant > 3) return fail(MX_EINVAL, "variant must be 0, 1, 2 or 3");
+    if (c->variant == 1 && c->sweeps_per_pass > 8)
+        return fail(MX_EINVAL, "the LDS-tile kernel runs at most 8 sweeps per pass");
     if (c->ndim == 3 && c->sweeps_per_pass > 1) return fail(MX_EINVAL, "3D grids run one sweep per pass");
     if (!(c->dt > 0.0) || !std::isfinite(c->dt)) return fail(MX_EINVAL, "dt must be positive and finite");
     double s = 0.0;
@@ -264,7 +286,7 @@ int mx_init(const mx_config *cfg, void *stream, void *workspace, size_t workspac
     g->bound = false;
     g->has_j = false;
     g->variant = cfg->variant > 0 ? cfg->variant : 2;
-    g->spp = cfg->sweeps_per_pass > 0 ? cfg->sweeps_per_pass : default_spp(cfg);
+    pass_depths(cfg, g->variant, g->spp);
     const size_t arr = up((size_t)g->ncell * elem_of(cfg));
     char *p = g->ws;
     auto take = [&](void **dst) { *dst = p; p += arr; };
@@ -328,7 +350,16 @@ int mx_set_step(mx_grid *g, int64_t n)
 int mx_get_sweeps_per_pass(mx_grid *g, int *k)
 {
     if (!g || !k) return fail(MX_EINVAL, "NULL argument");
-    *k = g->spp;
+    const mx_config &c = g->cfg;
+    *k = (c.ndim == 3 || (c.blocks & 1)) ? g->spp[0] : g->spp[1];
+    return MX_OK;
+}
+
+int mx_get_block_sweeps_per_pass(mx_grid *g, int k[2])
+{
+    if (!g || !k) return fail(MX_EINVAL, "NULL argument");
+    k[0] = g->spp[0];
+    k[1] = g->spp[1];
     return MX_OK;
 }
 
@@ -379,92 +410,106 @@ int block_mask_comps(int ndim, int b) { return ndim == 3 ? 7 : (b == 0 ? 3 : 4);
 
 // Run the sweeps of one solve: x = sum_{j<count} A^j b per block (Alg 1).
 // rhs: the right-hand side (dE' or Ebar).  Writes the per-block result
-// pointers into res[3].  When fuse_E is set and every block finishes in one
-// final pass, E += result is fused into that pass and *e_done is set.
+// pointers into res[3].  When E_fuse is set (fixed count), E += result is
+// fused into a block's final pass and e_done[block] is set.
+//
+// The blocks of a 2D grid are independent: the row-streaming kernel runs the
+// passes of each block on its own (groups {TE}, {TM}); the LDS-tile kernel
+// and 3D run all blocks together (one group).  With a fixed count, a group's
+// m sweeps are cut into the fewest passes of at most spp sweeps, of nearly
+// equal depth; under a tolerance every pass but the last is spp deep.
 template <typename T>
 int run_sweeps(mx_grid *g, void *const rhs[3], const int *target_in, bool tolmode, const double *rhsn,
-               void *E_fuse[3], bool *e_done, const T **res, mx_step_stats *st)
+               void *E_fuse[3], bool e_done[2], const T **res, mx_step_stats *st)
 {
     const mx_config &c = g->cfg;
     const Coef<T> &k = coef<T>(g);
     const int nblk = c.ndim == 3 ? 1 : 2;
     const bool delta = c.form == MX_FORM_DELTA && tolmode;
+    const bool split = c.ndim == 2 && g->variant == 3;
     int target[2] = {0, 0}, done[2] = {0, 0}, cur[2] = {-1, -1};
-    bool conv[2] = {false, false};
+    bool conv[2] = {false, false}, fused[2] = {false, false};
     double resid[2] = {0.0, 0.0};
     bool active_cfg[2];
     for (int b = 0; b < 2; b++) {
         active_cfg[b] = b < nblk && (c.ndim == 3 || (c.blocks & (1 << b)));
         target[b] = active_cfg[b] ? target_in[b] : 0;
     }
-    *e_done = false;
-    for (;;) {
-        int act = 0, kk = 1 << 30;
-        for (int b = 0; b < nblk; b++)
-            if (active_cfg[b] && done[b] < target[b] && !conv[b]) {
-                act |= 1 << b;
-                kk = std::min(kk, target[b] - done[b]);
-            }
-        if (!act) break;
-        kk = std::min(kk, g->spp);
-        const bool first = (act & 1) ? done[0] == 0 : done[1] == 0;
-        bool all_finish = !tolmode && E_fuse != nullptr;
-        for (int b = 0; b < nblk; b++) {
-            if (!active_cfg[b]) continue;
-            if (!(act & (1 << b)) || done[b] + kk != target[b]) all_finish = false;
-        }
-        int flags = 0;
-        if (first) flags |= SW_FIRST;
-        if (tolmode) flags |= SW_RESID;
-        if (all_finish) flags |= SW_LAST; else flags |= SW_STORE;
-        const int cb = (act & 1) ? cur[0] : cur[1];
-        const int ob = cb == 0 ? 1 : 0;
-        SweepArgs<T> a{};
-        for (int q = 0; q < 3; q++) {
-            a.rhs[q] = (const T *)rhs[q];
-            a.x_in[q] = (const T *)(cb < 0 ? rhs[q] : g->X[cb][q]);
-            a.s_in[q] = (const T *)g->S[q];
-            a.x_out[q] = (T *)g->X[ob][q];
-            a.s_out[q] = (T *)g->S[q];
-            a.E[q] = E_fuse ? (T *)E_fuse[q] : nullptr;
-        }
-        a.partial = g->partial;
-        int nwg = 0;
-        hipError_t e;
-        {
-            // arrays touched per component: the iterate (or dE' on the first
-            // pass) with halo, dE' (standard form), the running sum (delta
-            // form), the stored iterate/sum, or E read and written
-            int arrs;
-            if (!delta) arrs = (first ? 1 : 2) + ((flags & SW_LAST) ? 2 : 1);
-            else arrs = (first ? 1 : 2) + ((flags & SW_LAST) ? 2 : 2);
-            const int ncomp = c.ndim == 3 ? 3 : ((act & 1) ? 2 : 0) + ((act & 2) ? 1 : 0);
-            ProfScope ps(g, MX_PROF_SWEEP, (double)g->ncell * sizeof(T) * arrs * ncomp);
-            if (c.ndim == 2 && g->variant == 1) e = launch_sweep2d<T>(k, act, kk, delta, flags, a, g->stream, &nwg);
-            else if (c.ndim == 2) e = launch_stream2d<T>(k, act, kk, delta, flags, a, g->stream, &nwg, 0);
-            else e = launch_sweep3d<T>(k, delta, flags, a, g->stream, &nwg);
-        }
-        if (e != hipSuccess) return fail(MX_EDEVICE, "sweep launch: %s", hipGetErrorString(e));
-        for (int b = 0; b < nblk; b++)
-            if (act & (1 << b)) { done[b] += kk; cur[b] = ob; }
-        if (all_finish) *e_done = true;
-        if (tolmode) {
-            {
-                ProfScope ps(g, MX_PROF_OTHER, 0.0);
-                HIPCHK(launch_reduce2(g->partial, nwg, g->red, g->stream));
-            }
-            double h[2];
-            HIPCHK(hipMemcpyAsync(h, g->red, sizeof(h), hipMemcpyDeviceToHost, g->stream));
-            HIPCHK(hipStreamSynchronize(g->stream));
+    const int groups[2] = {split ? 1 : 3, split ? 2 : 0};
+    for (int gi = 0; gi < 2; gi++) {
+        const int gmask = groups[gi];
+        if (!gmask) continue;
+        for (;;) {
+            int act = 0, rem = 1 << 30;
+            for (int b = 0; b < nblk; b++)
+                if ((gmask & (1 << b)) && active_cfg[b] && done[b] < target[b] && !conv[b]) {
+                    act |= 1 << b;
+                    rem = std::min(rem, target[b] - done[b]);
+                }
+            if (!act) break;
+            const int spp = (act & 1) ? g->spp[0] : g->spp[1];
+            const int kk = tolmode ? std::min(rem, spp) : (rem + (rem + spp - 1) / spp - 1) / ((rem + spp - 1) / spp);
+            const bool first = (act & 1) ? done[0] == 0 : done[1] == 0;
+            // E += x fused into this pass when every active block of the group ends here
+            bool fin = !tolmode && E_fuse != nullptr;
             for (int b = 0; b < nblk; b++) {
-                if (!(act & (1 << b))) continue;
-                resid[b] = std::sqrt(h[b]);
-                if (!std::isfinite(resid[b]))
-                    return fail(MX_ENONFINITE, "step %lld: residual of block %d is not finite", (long long)g->step, b);
-                if (resid[b] <= c.tol * rhsn[b]) conv[b] = true;
+                if (!(gmask & (1 << b)) || !active_cfg[b]) continue;
+                if (!(act & (1 << b)) || done[b] + kk != target[b]) fin = false;
+            }
+            int flags = 0;
+            if (first) flags |= SW_FIRST;
+            if (tolmode) flags |= SW_RESID;
+            if (fin) flags |= SW_LAST; else flags |= SW_STORE;
+            const int cb = (act & 1) ? cur[0] : cur[1];
+            const int ob = cb == 0 ? 1 : 0;
+            SweepArgs<T> a{};
+            for (int q = 0; q < 3; q++) {
+                a.rhs[q] = (const T *)rhs[q];
+                a.x_in[q] = (const T *)(cb < 0 ? rhs[q] : g->X[cb][q]);
+                a.s_in[q] = (const T *)g->S[q];
+                a.x_out[q] = (T *)g->X[ob][q];
+                a.s_out[q] = (T *)g->S[q];
+                a.E[q] = E_fuse ? (T *)E_fuse[q] : nullptr;
+            }
+            a.partial = g->partial;
+            int nwg = 0;
+            hipError_t e;
+            {
+                // arrays touched per component: the iterate (or dE' on the first
+                // pass) with halo, dE' (standard form), the running sum (delta
+                // form), the stored iterate/sum, or E read and written
+                int arrs;
+                if (!delta) arrs = (first ? 1 : 2) + ((flags & SW_LAST) ? 2 : 1);
+                else arrs = (first ? 1 : 2) + ((flags & SW_LAST) ? 2 : 2);
+                const int ncomp = c.ndim == 3 ? 3 : ((act & 1) ? 2 : 0) + ((act & 2) ? 1 : 0);
+                ProfScope ps(g, MX_PROF_SWEEP, (double)g->ncell * sizeof(T) * arrs * ncomp);
+                if (c.ndim == 2 && g->variant == 1) e = launch_sweep2d<T>(k, act, kk, delta, flags, a, g->stream, &nwg);
+                else if (c.ndim == 2) e = launch_stream2d<T>(k, act, kk, delta, flags, a, g->stream, &nwg, 0);
+                else e = launch_sweep3d<T>(k, delta, flags, a, g->stream, &nwg);
+            }
+            if (e != hipSuccess) return fail(MX_EDEVICE, "sweep launch: %s", hipGetErrorString(e));
+            for (int b = 0; b < nblk; b++)
+                if (act & (1 << b)) { done[b] += kk; cur[b] = ob; fused[b] = fin; }
+            if (tolmode) {
+                {
+                    ProfScope ps(g, MX_PROF_OTHER, 0.0);
+                    HIPCHK(launch_reduce2(g->partial, nwg, g->red, g->stream));
+                }
+                double h[2];
+                HIPCHK(hipMemcpyAsync(h, g->red, sizeof(h), hipMemcpyDeviceToHost, g->stream));
+                HIPCHK(hipStreamSynchronize(g->stream));
+                for (int b = 0; b < nblk; b++) {
+                    if (!(act & (1 << b))) continue;
+                    resid[b] = std::sqrt(h[b]);
+                    if (!std::isfinite(resid[b]))
+                        return fail(MX_ENONFINITE, "step %lld: residual of block %d is not finite",
+                                    (long long)g->step, b);
+                    if (resid[b] <= c.tol * rhsn[b]) conv[b] = true;
+                }
             }
         }
     }
+    for (int b = 0; b < 2; b++) e_done[b] = fused[b];
     for (int q = 0; q < 3; q++) {
         const int b = c.ndim == 3 ? 0 : (q == 2 ? 1 : 0);
         if (done[b] == 0) res[q] = (const T *)rhs[q];
@@ -567,15 +612,17 @@ int step_impl(mx_grid *g, int nsteps, const double *env, const int *replay, mx_s
             if (target[b] < 0) return fail(MX_EINVAL, "negative replayed sweep count at step %d", s);
         }
         const T *res[3];
-        bool e_done = false;
+        bool e_done[2] = {false, false};
         mx_step_stats st{};
-        int rc = run_sweeps<T>(g, g->dEp, target, tolmode, rhsn, g->E, &e_done, res,
+        int rc = run_sweeps<T>(g, g->dEp, target, tolmode, rhsn, g->E, e_done, res,
                                stats ? &st : nullptr);
         if (rc) return rc;
-        if (!e_done) {
-            // E += dE per block (the components of inactive 2D blocks are left alone)
+        {
+            // E += dE per block not fused into its last pass (the components
+            // of inactive 2D blocks are left alone)
             for (int b = 0; b < nblk; b++) {
                 if (c.ndim == 2 && !(c.blocks & (1 << b))) continue;
+                if (e_done[b]) continue;
                 const int mask = block_mask_comps(c.ndim, b);
                 hipError_t er;
                 {
@@ -609,9 +656,9 @@ int adjoint_impl(mx_grid *g, int nsteps, const double *env, const int *sweeps, v
     for (int s = nsteps - 1; s >= 0; s--) {
         int target[2] = {sweeps[2 * s], sweeps[2 * s + 1]};
         const T *v[3];
-        bool e_done = false;
+        bool e_done[2] = {false, false};
         // v = P Ebar
-        int rc = run_sweeps<T>(g, Ebar, target, false, nullptr, nullptr, &e_done, v, nullptr);
+        int rc = run_sweeps<T>(g, Ebar, target, false, nullptr, nullptr, e_done, v, nullptr);
         if (rc) return rc;
         const double arr = (double)g->ncell * sizeof(T);
         {

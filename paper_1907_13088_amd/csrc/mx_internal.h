@@ -116,9 +116,12 @@ hipError_t launch_front_stream2d(const Coef<T> &c, int blocks, int filter_passes
 template <typename T>
 hipError_t launch_sweep2d(const Coef<T> &c, int blocks, int k, bool delta, int flags,
                           const SweepArgs<T> &a, hipStream_t s, int *nwg);
+// one pass of k sweeps over a block set (1 TE, 2 TM, 3 both) with the
+// row-streaming kernel; k in [1, stream2d_kmax(...)]
 template <typename T>
-hipError_t launch_stream2d(const Coef<T> &c, int blocks, int k, bool delta, int flags, const SweepArgs<T> &a,
+hipError_t launch_stream2d(const Coef<T> &c, int block, int k, bool delta, int flags, const SweepArgs<T> &a,
                            hipStream_t s, int *nwg, int slots);
+int stream2d_kmax(bool f64, int block, bool delta);
 template <typename T>
 hipError_t launch_update(int64_t n, int comp_mask, T *const E[3], const T *const X[3], hipStream_t s);
 

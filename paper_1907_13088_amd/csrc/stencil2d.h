@@ -31,4 +31,17 @@ __device__ __forceinline__ T a_tm(T czx, T czy, T czz, T lx, T ly, T lxy)
     return fmad(czz, lxy, fmad(czy, ly, czx * lx));
 }
 
+// b + (A x) with b as the innermost addend of the FMA chain (standard form)
+template <typename T>
+__device__ __forceinline__ T a_te_x_b(T cxx, T cxy, T lyy, T dg, T b) { return fmad(cxx, lyy, fmad(cxy, dg, b)); }
+
+template <typename T>
+__device__ __forceinline__ T a_te_y_b(T cyy, T cxy, T lxx, T dh, T b) { return fmad(cyy, lxx, fmad(cxy, dh, b)); }
+
+template <typename T>
+__device__ __forceinline__ T a_tm_b(T czx, T czy, T czz, T lx, T ly, T lxy, T b)
+{
+    return fmad(czz, lxy, fmad(czy, ly, fmad(czx, lx, b)));
+}
+
 }  // namespace mx

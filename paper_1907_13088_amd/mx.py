@@ -20,12 +20,12 @@ MX_OK, MX_EINVAL, MX_ECFL, MX_EWORKSPACE, MX_EDEVICE, MX_ENONFINITE, MX_ESTATE =
 MX_F32, MX_F64 = 0, 1
 MX_TE, MX_TM, MX_ALL = 1, 2, 3
 FORM_STANDARD, FORM_DELTA = 0, 1
-VARIANT_AUTO, VARIANT_TILE, VARIANT_STREAM = 0, 1, 2
+VARIANT_AUTO, VARIANT_TILE, VARIANT_STREAM, VARIANT_STREAM_BLOCK = 0, 1, 2, 3
 WARN_NOCONV_GUARANTEE = 1
 
 EXPORTS = ["mx_profile_enable", "mx_profile_read", "mx_last_error", "mx_config_default", "mx_validate", "mx_workspace_size", "mx_init",
            "mx_bind_fields", "mx_set_current", "mx_step", "mx_get_step", "mx_set_step",
-           "mx_get_sweeps_per_pass", "mx_destroy", "mx_adjoint", "mx_sources_assemble",
+           "mx_get_sweeps_per_pass", "mx_get_block_sweeps_per_pass", "mx_destroy", "mx_adjoint", "mx_sources_assemble",
            "mx_sources_project", "mx_batch_workspace_size", "mx_batch_init", "mx_batch_bind",
            "mx_batch_step", "mx_batch_get_plan", "mx_batch_destroy"]
 
@@ -83,6 +83,7 @@ def lib():
         L.mx_get_step.argtypes = [vp, P(C.c_int64)]
         L.mx_set_step.argtypes = [vp, C.c_int64]
         L.mx_get_sweeps_per_pass.argtypes = [vp, P(C.c_int)]
+        L.mx_get_block_sweeps_per_pass.argtypes = [vp, P(C.c_int)]
         L.mx_destroy.argtypes = [vp]
         L.mx_profile_enable.argtypes = [vp, C.c_int]
         L.mx_profile_read.argtypes = [vp, P(CProfile)]
@@ -274,6 +275,13 @@ class Grid:
         k = C.c_int()
         _check(lib().mx_get_sweeps_per_pass(self.h, C.byref(k)))
         return k.value
+
+    @property
+    def block_sweeps_per_pass(self) -> tuple:
+        """(TE, TM) sweeps per pass (3D: first entry)."""
+        k = (C.c_int * 2)()
+        _check(lib().mx_get_block_sweeps_per_pass(self.h, k))
+        return (k[0], k[1])
 
     def close(self):
         if getattr(self, "h", None):

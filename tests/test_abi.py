@@ -51,7 +51,8 @@ def _cfg(**kw):
     (dict(sweeps=-1), mx.MX_EINVAL),
     (dict(tol=-1e-3), mx.MX_EINVAL),
     (dict(filter_passes=9), mx.MX_EINVAL),
-    (dict(sweeps_per_pass=9), mx.MX_EINVAL),
+    (dict(sweeps_per_pass=17), mx.MX_EINVAL),
+    (dict(sweeps_per_pass=9, variant=1), mx.MX_EINVAL),
     (dict(form=7), mx.MX_EINVAL),
     (dict(ndim=3, n=(8, 8, 8), dt=0.5 / math.sqrt(3), blocks=1), mx.MX_EINVAL),
     (dict(ndim=3, n=(8, 8, 8), dt=0.99 / math.sqrt(2)), mx.MX_ECFL),

@@ -15,7 +15,7 @@ import pytest
 from paper_1907_13088_amd import inputs as I
 from paper_1907_13088_amd import mx
 
-from gpu_helpers import log, rel_err, run_gpu, run_oracle
+from gpu_helpers import gpu_config, log, rel_err, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -49,13 +49,28 @@ def test_te_planewave_fp64_tolerance_replay_and_decisions():
     assert all(s.sweeps[0] > 20 for s in sto)
 
 
-@pytest.mark.parametrize("variant", [mx.VARIANT_TILE, mx.VARIANT_STREAM])
-@pytest.mark.parametrize("spp", [1, 2, 3, 4, 5, 6, 7, 8])
+# deepest FP64 streaming pass (TE, TM), standard form: both blocks in one
+# pass, or each block on its own
+KMAX_F64 = {mx.VARIANT_STREAM: (3, 3), mx.VARIANT_STREAM_BLOCK: (5, 8)}
+VARIANTS = [mx.VARIANT_TILE, mx.VARIANT_STREAM, mx.VARIANT_STREAM_BLOCK]
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("spp", [1, 2, 3, 4, 5, 6, 7, 8, 16])
 def test_modes_fp64_every_pass_depth(small_modes, spp, variant):
     w = small_modes
     nsteps = 12
+    if variant == mx.VARIANT_TILE and spp > 8:
+        pytest.skip("the LDS-tile kernel fuses at most 8 sweeps")
+    if variant == mx.VARIANT_STREAM and spp > 4:
+        pytest.skip("covered by the smaller depths (capped at 3)")
+    cfg = gpu_config(w, spp=spp, variant=variant)
+    g = mx.Grid(cfg)
+    want = (spp, spp) if variant == mx.VARIANT_TILE else tuple(min(spp, k) for k in KMAX_F64[variant])
+    assert g.block_sweeps_per_pass == want
+    g.close()
     Eg, Bg, _, k = run_gpu(w, nsteps, spp=spp, variant=variant)
-    assert k == spp
+    assert k == want[0]
     Eo, Bo, _ = run_oracle(w, nsteps)
     e = rel_err(Eg + Bg, Eo + Bo)
     log(f"variant={variant} spp={spp} fp64 errors {max(e):.3e}")
@@ -67,8 +82,8 @@ def test_pass_depth_and_kernel_invariance_is_bitwise(small_modes):
     where iterates live, not the arithmetic: FP32 results are bitwise equal."""
     w = small_modes
     ref_out = None
-    for variant in (mx.VARIANT_TILE, mx.VARIANT_STREAM):
-        for spp in (1, 3, 5, 8):
+    for variant in VARIANTS:
+        for spp in (1, 3, 5, 8) + ((0, 9, 12, 16) if variant == mx.VARIANT_STREAM_BLOCK else (0,)):
             Eg, Bg, _, _ = run_gpu(w, 6, dtype="f32", spp=spp, variant=variant)
             if ref_out is None:
                 ref_out = (Eg, Bg)
@@ -104,6 +119,21 @@ def test_single_block(small_modes, blocks):
         assert np.array_equal(arr_g, arr_in)
 
 
+def test_replayed_counts_differ_per_block(small_modes):
+    """Per-step, per-block sweep counts including 0 (no sweep: E += dE'),
+    odd counts and counts deeper than one pass: the E update is fused into
+    a block's last pass or done apart, per block."""
+    w = small_modes
+    counts = [(0, 5), (17, 0), (1, 33), (23, 2), (0, 0), (10, 16)]
+    Eo, Bo, _ = run_oracle(w, len(counts), replay=counts)
+    for variant in VARIANTS:
+        Eg, Bg, st, _ = run_gpu(w, len(counts), replay=counts, variant=variant)
+        assert [tuple(s.sweeps) for s in st] == counts
+        e = rel_err(Eg + Bg, Eo + Bo)
+        log(f"variant={variant} per-block replay errors {max(e):.2e}")
+        assert max(e) < 1e-12
+
+
 def test_lumped_yee(small_modes):
     w = small_modes
     Eg, Bg, st, _ = run_gpu(w, 10, lumped=True)
@@ -112,7 +142,7 @@ def test_lumped_yee(small_modes):
     assert all(s.sweeps == (0, 0) for s in st)
 
 
-@pytest.mark.parametrize("variant", [mx.VARIANT_TILE, mx.VARIANT_STREAM])
+@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("form", [mx.FORM_STANDARD, mx.FORM_DELTA])
 def test_tolerance_mode_small(small_modes, form, variant):
     w = small_modes
