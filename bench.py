@@ -2,17 +2,20 @@
 """Throughput of the finite-element Maxwell field step on one MI355X.
 
 Workload: 2D periodic 4096 x 4096 grid, FP32, TE+TM (six components),
-Courant 0.5 (dt = 0.5 dt_CFL), initial fields = 256 seeded plane waves with
-|k| <= pi/2 and N(0,1) amplitudes, prescribed current = 64 seeded Gaussian
-pulses (sigma = 8 cells, sin(0.3 t) envelope), 3-pass binomial current
-filter every step, m = 20 mass-matrix sweeps per step.
+Courant 0.5 (dt = 0.5 dt_CFL), initial fields = 256 seeded Fourier modes
+with |k| <= pi/2 and N(0,1) amplitudes, prescribed current = 64 seeded
+Gaussian pulses (sigma = 8 cells, sin(0.3 t) envelope), 3-pass binomial
+current filter every step, m = 20 mass-matrix sweeps per step.
 
 A step is one full time step: filter + Faraday + auxiliary increment, the
 20 sweeps, and the E increment.  Inputs are resident in HBM before timing.
-Reported: Gcell-steps/s (cells x steps / s), FP64 throughput and the FP32
-error against the FP64 path on the same inputs, the sweep kernel's achieved
-bandwidth against the 8 TB/s HBM peak (HIP events on the library stream),
-and the FP64 CPU oracle timed on this host's cores on a bounded sample.
+Reported: Gcell-steps/s (cells x steps / s) in FP32, the same for the FP64
+path and the FP32 error against it after the same steps, per-kernel times
+from HIP events recorded on the library stream inside the timed region, the
+roofline of the dominant kernel (the sweep pass that stores its iterate)
+with HBM traffic read from the committed rocprofv3 counter summary when the
+kernel sources still match it, and the FP64 CPU oracle timed on this
+host's cores on a bounded sample.
 
     python bench.py [--gpus 1] [--steps 1000] [--warmup 20]
 """
@@ -20,12 +23,16 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
 
 HBM_PEAK_GBS = 8000.0
+# FP32 FMA issue rate without the packed two-wide forms (not used in this
+# build): 256 CUs x 64 lanes x 2 flops x 2.4 GHz
+VALU_FP32_PEAK_TFLOPS = 78.6
+HERE = os.path.dirname(os.path.abspath(__file__))
+PROFILE_SUMMARY = os.path.join(HERE, "profiles", "sweep_pass_2d_4096sq_f32.md")
 
 
 def log(msg):
@@ -42,8 +49,8 @@ def main():
     ap.add_argument("--variant", type=int, default=0,
                     help="2D sweep kernel: 0 library choice, 1 LDS tile, 2 row streaming, "
                          "3 row streaming per block")
-    ap.add_argument("--profile-steps", type=int, default=50)
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="minimum CPU time of the oracle sample (whole steps, at most 8)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -52,15 +59,15 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs the field step on one GPU only; a multi-GPU run "
-              "(spatial domain decomposition with halo exchange) is not built", file=sys.stderr)
+        print("bench.py: the field step runs on one GPU; a multi-GPU run (spatial domain "
+              "decomposition with halo exchange) is not part of this library", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1907_13088_amd import inputs as I
     from paper_1907_13088_amd import mx
+    from paper_1907_13088_amd import profsum
 
     mx.lib()  # raises if the HIP library is missing: no fallback path exists
     if not torch.cuda.is_available():
@@ -81,7 +88,7 @@ def main():
     K, W = args.steps, args.warmup
     n = args.n
     t0 = time.time()
-    w = I.modes_2d((n, n), steps=W + K + args.profile_steps, dtype="f32")
+    w = I.modes_2d((n, n), steps=W + K, dtype="f32")
     log(f"inputs generated in {time.time() - t0:.1f}s")
     env = [float(x) for x in w.env]
     ncell = n * n
@@ -102,6 +109,8 @@ def main():
         g, E, B, J = make(dtype)
         g.step(W, env[:W])
         torch.cuda.synchronize()
+        # per-launch HIP events on the library stream over the timed steps
+        g.profile_enable(True)
         s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         wall0 = time.perf_counter()
         s0.record()
@@ -109,60 +118,70 @@ def main():
         s1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - wall0
+        prof = g.profile_read()
+        g.profile_enable(False)
         ms = s0.elapsed_time(s1)
-        log(f"{dtype}: {K} steps in {ms:.1f} ms (wall {wall * 1e3:.1f} ms), spp={g.sweeps_per_pass}")
-        return g, E, B, J, ms
+        log(f"{dtype}: {K} steps in {ms:.1f} ms (wall {wall * 1e3:.1f} ms), "
+            f"sweeps per pass {g.block_sweeps_per_pass}")
+        return g, E, B, J, ms, prof
 
-    g32, E32, B32, J32, ms32 = timed("f32")
+    g32, E32, B32, J32, ms32, prof = timed("f32")
     value = ncell * K / (ms32 / 1e3) / 1e9
 
     fp64 = None
     if not args.no_fp64:
-        g64, E64, B64, J64, ms64 = timed("f64")
+        g64, E64, B64, J64, ms64, _ = timed("f64")
         scale = max(float(t.abs().max()) for t in E64 + B64)
         err = max(float((a.double() - b).abs().max()) for a, b in zip(E32 + B32, E64 + B64)) / scale
-        fp64 = {"value": ncell * K / (ms64 / 1e3) / 1e9, "ms_per_step": ms64 / K,
-                "fp32_vs_fp64_rel_err": err, "err_steps": W + K}
+        fp64 = {"value": round(ncell * K / (ms64 / 1e3) / 1e9, 3), "ms_per_step": round(ms64 / K, 5),
+                "fp32_vs_fp64_rel_err": err, "err_steps": W + K,
+                "err_metric": "max |FP32 - FP64| over the six components / max |FP64|"}
         log(f"f64: {fp64['value']:.2f} Gcell-steps/s; FP32 vs FP64 normwise rel err after {W + K} steps: {err:.2e}")
         g64.close()
         del E64, B64, J64
 
-    # per-kernel times on the library stream (separate run, so the headline
-    # timing carries no event overhead)
-    g32.profile_enable(True)
-    P = args.profile_steps
-    g32.step(P, env[W + K:W + K + P])
-    prof = g32.profile_read()
-    g32.profile_enable(False)
-    sw = prof["sweep"]
-    achieved = sw["bytes"] / (sw["ms"] / 1e3) / 1e9 if sw["ms"] > 0 else 0.0
+    total_ms = sum(v["ms"] for v in prof.values())
     kernels = {}
     for name, v in prof.items():
         if v["launches"]:
-            kernels[name] = {"launches": v["launches"], "avg_us": 1e3 * v["ms"] / v["launches"],
-                             "GBps": v["bytes"] / (v["ms"] / 1e3) / 1e9 if v["ms"] > 0 else None,
-                             "share": v["ms"] / sum(x["ms"] for x in prof.values())}
+            kernels[name] = {"launches": v["launches"], "avg_us": round(1e3 * v["ms"] / v["launches"], 2),
+                             "GBps": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None,
+                             "share": round(v["ms"] / total_ms, 4)}
     log(f"kernels: {json.dumps(kernels)}")
+    sw = prof["sweep"]
+    nl = max(sw["launches"], 1)
+    avg_s = sw["ms"] / 1e3 / nl
+    bytes_per_launch = sw["bytes"] / nl
+    achieved = bytes_per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
+    k = g32.block_sweeps_per_pass[0]
+    traffic = profsum.traffic_per_launch(PROFILE_SUMMARY)
+    # FP32 flops of one sweep of the implemented stencils (an FMA counts 2):
+    # TE 18 per cell (Ex 9, Ey 9), TM 15 per cell
+    flops_per_launch = 33.0 * ncell * k
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k2_sweep (mass-matrix sweep pass)",
-                "bytes_per_launch": sw["bytes"] / max(sw["launches"], 1),
-                "avg_launch_us": 1e3 * sw["ms"] / max(sw["launches"], 1)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": f"k2_stream<float,3,{k}> row-streaming pass of {k} sweeps storing its iterate",
+                "bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_s * 1e6, 2), "launches": nl,
+                "valu_tflops": round(flops_per_launch / avg_s / 1e12, 2) if avg_s > 0 else None,
+                "valu_peak_tflops": VALU_FP32_PEAK_TFLOPS,
+                "step_hbm_GBps": round(sum(v["bytes"] for v in prof.values()) / (total_ms / 1e3) / 1e9, 1)}
 
     cpu = None
-    if not args.no_cpu_baseline and args.cpu_steps > 0:
+    if not args.no_cpu_baseline:
         from oracle import ref
         cfg = ref.Config(ndim=2, shape=w.shape, dt=w.dt, sweeps=w.sweeps, filter_passes=w.filter_passes)
-        E = [a.copy() for a in w.E]
-        B = [a.copy() for a in w.B]
+        E = [a.astype("float64") for a in w.E]
+        B = [a.astype("float64") for a in w.B]
+        J0 = [a.astype("float64") for a in w.J0]
         c0 = time.perf_counter()
-        for s in range(args.cpu_steps):
-            ref.step(cfg, E, B, w.J0, env[s])
+        steps = 0
+        while steps < 8 and (steps == 0 or time.perf_counter() - c0 < args.cpu_seconds):
+            ref.step(cfg, E, B, J0, env[steps])
+            steps += 1
         ct = time.perf_counter() - c0
-        cpu = {"value": ncell * args.cpu_steps / ct / 1e9, "unit": "Gcell-steps/s", "cores": ref.num_threads(),
+        cpu = {"value": ncell * steps / ct / 1e9, "unit": "Gcell-steps/s", "cores": ref.num_threads(),
                "kind": "oracle",
-               "sample": f"{args.cpu_steps} steps of the same {n}x{n} workload, FP64 C oracle, "
-                         f"{ct:.1f} s"}
+               "sample": f"first {steps} steps of the same {n}x{n} workload, FP64 C oracle, {ct:.1f} s"}
         log(f"cpu oracle: {cpu}")
 
     out = {
@@ -178,10 +197,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"2D periodic {n}x{n} TE+TM FP32, Courant 0.5, 256 plane waves |k|<=pi/2, "
+        "config": {"workload": f"2D periodic {n}x{n} TE+TM FP32, Courant 0.5, 256 Fourier modes |k|<=pi/2, "
                                f"64 Gaussian current pulses, 3-pass binomial filter, m=20 sweeps",
                    "grid": [n, n], "sweeps": w.sweeps, "filter_passes": w.filter_passes,
-                   "sweeps_per_pass": g32.sweeps_per_pass, "parallelism": "single GPU"},
+                   "sweeps_per_pass": list(g32.block_sweeps_per_pass), "parallelism": "single GPU"},
         "fp64": fp64,
         "roofline": roofline,
         "kernels": kernels,

@@ -166,14 +166,16 @@ int mx_destroy(mx_grid *g);
  * touched cell) is added to its category.  mx_profile_enable resets the
  * counters; mx_profile_read waits for the stream and sums the event times.
  * ------------------------------------------------------------------------ */
-#define MX_PROF_FRONT   0   /* filter + Faraday + auxiliary increment */
-#define MX_PROF_SWEEP   1   /* mass-matrix sweep passes (E increment fused) */
-#define MX_PROF_OTHER   2   /* separate E increments, FP64 reductions, copies */
-#define MX_PROF_ADJOINT 3   /* transposed curls and the filter of the adjoint */
+#define MX_PROF_FRONT      0  /* filter + Faraday + auxiliary increment */
+#define MX_PROF_SWEEP      1  /* mass-matrix sweep passes that store the iterate */
+#define MX_PROF_OTHER      2  /* separate E increments, FP64 reductions, copies */
+#define MX_PROF_ADJOINT    3  /* transposed curls and the filter of the adjoint */
+#define MX_PROF_SWEEP_LAST 4  /* final sweep passes with E += result fused */
+#define MX_PROF_NCAT       5
 typedef struct mx_profile {
-    int64_t launches[4];
-    double ms[4];         /* summed kernel time per category */
-    double bytes[4];      /* summed algorithmic bytes per category */
+    int64_t launches[MX_PROF_NCAT];
+    double ms[MX_PROF_NCAT];     /* summed kernel time per category */
+    double bytes[MX_PROF_NCAT];  /* summed algorithmic bytes per category */
 } mx_profile;
 
 int mx_profile_enable(mx_grid *g, int on);

@@ -118,8 +118,8 @@ struct mx_grid {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<int> ev_cat;          // category per event pair
-    int64_t launches[4] = {0, 0, 0, 0};
-    double bytes[4] = {0, 0, 0, 0};
+    int64_t launches[MX_PROF_NCAT] = {};
+    double bytes[MX_PROF_NCAT] = {};
 };
 
 namespace {
@@ -377,7 +377,7 @@ int mx_profile_enable(mx_grid *g, int on)
     g->prof = on != 0;
     g->ev_used = 0;
     g->ev_cat.clear();
-    for (int i = 0; i < 4; i++) { g->launches[i] = 0; g->bytes[i] = 0.0; }
+    for (int i = 0; i < MX_PROF_NCAT; i++) { g->launches[i] = 0; g->bytes[i] = 0.0; }
     return MX_OK;
 }
 
@@ -386,7 +386,7 @@ int mx_profile_read(mx_grid *g, mx_profile *out)
     if (!g || !out) return fail(MX_EINVAL, "NULL argument");
     HIPCHK(hipSetDevice(g->device));
     HIPCHK(hipStreamSynchronize(g->stream));
-    for (int i = 0; i < 4; i++) { out->launches[i] = g->launches[i]; out->bytes[i] = g->bytes[i]; out->ms[i] = 0.0; }
+    for (int i = 0; i < MX_PROF_NCAT; i++) { out->launches[i] = g->launches[i]; out->bytes[i] = g->bytes[i]; out->ms[i] = 0.0; }
     for (size_t p = 0; p < g->ev_cat.size(); p++) {
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, g->ev_pool[2 * p], g->ev_pool[2 * p + 1]));
@@ -482,7 +482,8 @@ int run_sweeps(mx_grid *g, void *const rhs[3], const int *target_in, bool tolmod
                 if (!delta) arrs = (first ? 1 : 2) + ((flags & SW_LAST) ? 2 : 1);
                 else arrs = (first ? 1 : 2) + ((flags & SW_LAST) ? 2 : 2);
                 const int ncomp = c.ndim == 3 ? 3 : ((act & 1) ? 2 : 0) + ((act & 2) ? 1 : 0);
-                ProfScope ps(g, MX_PROF_SWEEP, (double)g->ncell * sizeof(T) * arrs * ncomp);
+                ProfScope ps(g, (flags & SW_LAST) ? MX_PROF_SWEEP_LAST : MX_PROF_SWEEP,
+                             (double)g->ncell * sizeof(T) * arrs * ncomp);
                 if (c.ndim == 2 && g->variant == 1) e = launch_sweep2d<T>(k, act, kk, delta, flags, a, g->stream, &nwg);
                 else if (c.ndim == 2) e = launch_stream2d<T>(k, act, kk, delta, flags, a, g->stream, &nwg, 0);
                 else e = launch_sweep3d<T>(k, delta, flags, a, g->stream, &nwg);

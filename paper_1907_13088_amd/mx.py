@@ -44,10 +44,10 @@ class CConfig(C.Structure):
 
 
 class CProfile(C.Structure):
-    _fields_ = [("launches", C.c_int64 * 4), ("ms", C.c_double * 4), ("bytes", C.c_double * 4)]
+    _fields_ = [("launches", C.c_int64 * 5), ("ms", C.c_double * 5), ("bytes", C.c_double * 5)]
 
 
-PROF_CATEGORIES = ("front", "sweep", "other", "adjoint")
+PROF_CATEGORIES = ("front", "sweep", "other", "adjoint", "sweep_last")
 
 
 class CStats(C.Structure):

@@ -1,0 +1,157 @@
+"""Text summaries of rocprofv3 runs of bench.py (kernel trace statistics and
+HBM traffic from the FETCH_SIZE / WRITE_SIZE counters), and the lookup that
+bench.py uses to attach the measured traffic to its roofline line.
+
+rocprofv3 writes one SQLite database per run (``-d DIR -o run``).  Traffic
+is the counter value (KiB per dispatch) scaled by what the same counter
+reads for a plain device copy of known size in the same run (bench.py
+--copy-probe BYTES), per kernel launch.  A summary records a hash of the
+kernel sources it was measured on; once they change, the lookup returns
+None so that no stale traffic is reported.
+
+    python -m paper_1907_13088_amd.profsum --trace T.db --fetch F.db --write W.db \\
+        --copy-bytes N --bench-json bench.json --kernel REGEX --out profiles/NAME.md \\
+        --cmd-trace "..." --cmd-fetch "..." --cmd-write "..."
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sqlite3
+import statistics
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+# sources that determine the 2D sweep pass kernels and their launch shapes
+SWEEP_SOURCES = ("csrc/k2s_impl.h", "csrc/stencil2d.h", "csrc/mx_internal.h", "csrc/k2s.hip",
+                 "csrc/k2s_f32_all.hip", "csrc/mx_api.cpp")
+
+
+def source_sha(files=SWEEP_SOURCES) -> str:
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def traffic_per_launch(path: str):
+    """Measured HBM bytes per launch of the summarised kernel, or None when
+    the summary is missing or was taken on other kernel sources."""
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m1 = re.search(r"^traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt, re.M)
+    m2 = re.search(r"^source_sha256:\s*([0-9a-f]+)", txt, re.M)
+    if not m1 or not m2 or m2.group(1) != source_sha():
+        return None
+    return float(m1.group(1))
+
+
+def _short(n: str) -> str:
+    n = re.sub(r"\(.*", "", n)
+    return n.replace("void ", "").replace("mx::", "")
+
+
+def _stats(db):
+    cur = sqlite3.connect(db).cursor()
+    return list(cur.execute("select name, total_calls, total_duration, average, percentage from top_kernels"))
+
+
+def _counter(db, name):
+    cur = sqlite3.connect(db).cursor()
+    per = {}
+    for k, v in cur.execute("select kernel_name, value from counters_collection where counter_name = ?", (name,)):
+        per.setdefault(k, []).append(float(v))
+    return per
+
+
+def summarize(trace, fetch, write, copy_bytes, bench_json, kernel_re, out, cmds):
+    st = _stats(trace)
+    f = _counter(fetch, "FETCH_SIZE")
+    w = _counter(write, "WRITE_SIZE")
+    copyk = [k for k in f if "copy" in k.lower() and k in w]
+    if not copyk:
+        raise SystemExit("no copy kernel in the counter runs (run bench.py with --copy-probe)")
+    ck = max(copyk, key=lambda k: statistics.median(f[k]))
+    fcopy, wcopy = statistics.median(f[ck]), statistics.median(w[ck])
+    # the copy reads and writes copy_bytes: bytes per counter unit
+    ff, fw = copy_bytes / fcopy, copy_bytes / wcopy
+    bench = json.loads(open(bench_json).read().strip().splitlines()[-1]) if bench_json else None
+    L = []
+    L.append("# rocprofv3 summary: 2D field step, 4096 x 4096 TE+TM FP32, m = 20, p = 3 (MI355X, 1 GPU)")
+    L.append("")
+    L.append("kernel trace command: `" + cmds[0] + "`")
+    L.append("")
+    L.append("| kernel | calls | avg us | total ms | % |")
+    L.append("|---|---:|---:|---:|---:|")
+    sel = None
+    for n, c, tot, avg, pct in st:
+        L.append(f"| {_short(n)} | {c} | {avg:.1f} | {tot / 1e3:.2f} | {pct:.1f} |")
+        if sel is None and re.search(kernel_re, n):
+            sel = (n, c, avg)
+    L.append("")
+    if bench:
+        L.append("library HIP-event averages inside the timed region of the same command (bench.py output):")
+        L.append("")
+        L.append("| category | launches | avg us | algorithmic GB/s |")
+        L.append("|---|---:|---:|---:|")
+        for k, v in bench["kernels"].items():
+            L.append(f"| {k} | {v['launches']} | {v['avg_us']} | {v['GBps']} |")
+        L.append("")
+    L.append("HBM traffic per dispatch (one counter per run):")
+    L.append("")
+    L.append("fetch command: `" + cmds[1] + "`")
+    L.append("")
+    L.append("write command: `" + cmds[2] + "`")
+    L.append("")
+    L.append(f"calibration: a plain {copy_bytes}-byte device copy ({_short(ck)}) reads FETCH_SIZE = {fcopy:.0f} "
+             f"and WRITE_SIZE = {wcopy:.0f} per dispatch, so one unit is {ff:.1f} B read and {fw:.1f} B written")
+    L.append("")
+    L.append("| kernel | dispatches | read MB | written MB | traffic MB |")
+    L.append("|---|---:|---:|---:|---:|")
+    chosen = None
+    for k in sorted(f, key=lambda k: -statistics.mean(f[k])):
+        if k == ck or k not in w:
+            continue
+        rd = statistics.mean(f[k]) * ff
+        wr = statistics.mean(w[k]) * fw
+        L.append(f"| {_short(k)} | {len(f[k])} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | {(rd + wr) / 1e6:.1f} |")
+        if chosen is None and re.search(kernel_re, k):
+            chosen = (k, rd, wr)
+    L.append("")
+    if sel is None or chosen is None:
+        raise SystemExit(f"kernel /{kernel_re}/ not found in the runs")
+    L.append(f"dominant kernel: `{_short(sel[0])}`, {sel[1]} calls, rocprofv3 average {sel[2]:.1f} us")
+    if bench:
+        r = bench["roofline"]
+        L.append(f"bench.py HIP-event average of the same launches: {r['avg_launch_us']} us, "
+                 f"algorithmic {r['bytes_per_launch'] / 1e6:.1f} MB per launch ({r['achieved']} GB/s)")
+    L.append("")
+    L.append(f"traffic_bytes_per_launch: {chosen[1] + chosen[2]:.0f}")
+    L.append(f"source_sha256: {source_sha()}")
+    open(out, "w").write("\n".join(L) + "\n")
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--copy-bytes", type=int, required=True)
+    ap.add_argument("--bench-json", default=None)
+    ap.add_argument("--kernel", required=True, help="regex of the dominant kernel's name")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--cmd-trace", required=True)
+    ap.add_argument("--cmd-fetch", required=True)
+    ap.add_argument("--cmd-write", required=True)
+    a = ap.parse_args()
+    print(summarize(a.trace, a.fetch, a.write, a.copy_bytes, a.bench_json, a.kernel, a.out,
+                    (a.cmd_trace, a.cmd_fetch, a.cmd_write)))
+
+
+if __name__ == "__main__":
+    main()
