@@ -5,13 +5,12 @@ namespace mx {
 namespace {
 using namespace front2d;
 
-constexpr int FRX = 256;
+constexpr int FRX = 512;   // threads (columns) per workgroup strip
 
 template <typename T, int BLK, int P, bool HASJ>
 hipError_t front_j(const Coef<T> &c, const FrontArgs<T> &a, const T *const Bin[3], hipStream_t s, int *nwg)
 {
-    constexpr int HL = P > 1 ? P : 1, HR = P > 2 ? P : 2;
-    constexpr int W = FRX - HL - HR;
+    constexpr int W = front_aligned() ? FRX - 32 : FRX - (P > 1 ? P : 1) - (P > 2 ? P : 2);
     static int slots = -1;
     if (slots < 0) {
         int o = 0, dev = 0, cu = 0;

@@ -76,8 +76,9 @@ __device__ __forceinline__ void front_tile(const Coef<T> &c, const FrontArgs<T> 
                                            void *lds, double *sred)
 {
     constexpr bool TE = BLK & 1, TM = BLK & 2;
-    constexpr int HL = P > 1 ? P : 1, HR = P > 2 ? P : 2;
-    constexpr int W = RX - HL - HR;
+    constexpr int HL = front_aligned() ? 16 : (P > 1 ? P : 1);
+    constexpr int W = front_aligned() ? RX - 32 : RX - HL - (P > 2 ? P : 2);
+    static_assert(HL >= (P > 1 ? P : 1) && RX - HL - W >= (P > 2 ? P : 2), "the halo must cover the stencils");
     constexpr int PADL = P > 1 ? P : 1;
     constexpr int PR = RX + 2 * PADL;
     constexpr int D = P - 2;           // the current is loaded D rows ahead of E
@@ -94,7 +95,7 @@ __device__ __forceinline__ void front_tile(const Coef<T> &c, const FrontArgs<T> 
     const int X0 = sx * W, Y0 = sy * L;
     const int gxi = X0 - HL + i;
     const int gx = wrapi(gxi, nx);
-    const bool outcol = i >= HL && i < RX - HR && gxi < nx;
+    const bool outcol = i >= HL && i < HL + W && gxi < nx;
     constexpr bool hasj = HASJ;   // a prescribed current is present (a.J0 non-null)
     const T sixth = c.lumped ? T(0) : T(1.0 / 6.0);
     const T es = a.env_src;

@@ -62,8 +62,8 @@ struct alignas(2 * sizeof(T)) Pair {
     T x, y;
 };
 
-// rows in flight per thread (prefetch depth): two rows; deeper prefetch
-// measured no faster (the passes are issue bound, not latency bound)
+// rows in flight per thread (prefetch depth), a divisor of 6; three or six
+// rows measured no faster than two
 template <typename T, int BLK, int K>
 constexpr int stream_pf() { return 2; }
 
@@ -81,7 +81,9 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
                                             int wid, int pidx, void *lds, double *sred)
 {
     constexpr bool TE = BLK & 1, TM = BLK & 2;
-    constexpr int W = RX - 2 * K;
+    constexpr int H = stream_halo(K);          // columns left of the first output column
+    constexpr int W = stream_width<RX>(K);
+    static_assert(H >= K && RX - H - W >= K, "the halo must cover every level");
     constexpr int PAD = RX + 2;
     // column j of a level row sits at index j + 1 - (strip origin - K)
     Pair<T>(*xp)[2][PAD] = reinterpret_cast<Pair<T>(*)[2][PAD]>(lds);
@@ -92,13 +94,13 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
     const int nx = c.nx, ny = c.ny;
     const int i = threadIdx.x;
     const int X0 = sx * W, Y0 = sy * L;
-    const int gxi = X0 - K + i;
+    const int gxi = X0 - H + i;
     const int gx = wrapi(gxi, nx);
     const bool first = flags & SW_FIRST;
     constexpr bool last = OM == OM_LAST;
     constexpr bool resid = OM == OM_RESID;
     constexpr bool store = OM != OM_LAST;
-    const bool outcol = i >= K && i < RX - K && gxi < nx;
+    const bool outcol = i >= H && i < H + W && gxi < nx;
     const int rend = std::min(Y0 + L, ny);   // rows this item writes: [Y0, rend)
 
     T out[K + 1][3];
@@ -342,12 +344,12 @@ __global__ __launch_bounds__(RX) void k2_stream(Coef<T> c, SweepArgs<T> a, int f
     stream_tile<T, BLK, K, DELTA, RX, OM>(c, a, flags, L, nsx, xcd_item(nwg), blockIdx.x, lds, sred);
 }
 
-constexpr int SRX = 256;
+constexpr int SRX = 256;   // threads (columns) per workgroup strip
 
 template <typename T, int BLK, int K, bool DELTA, int OM>
 hipError_t stream_om(const Coef<T> &c, int flags, const SweepArgs<T> &a, hipStream_t s, int *nwg, int slots)
 {
-    constexpr int W = SRX - 2 * K;
+    constexpr int W = stream_width<SRX>(K);
     static int occ = -1, ncu = -1;
     if (occ < 0) {
         int o = 0, dev = 0, cu = 0;

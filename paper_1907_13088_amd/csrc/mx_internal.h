@@ -91,10 +91,22 @@ struct GridDesc {
     int nsx_f, nsx_s; // strips of the front and of the sweep pass
 };
 
+// Strip geometry of the row-streaming kernels.  An aligned strip writes a
+// 128-byte aligned run of RX - 32 columns (16 halo columns on each side), so
+// no cache line is written partly by two workgroups (on different XCDs);
+// this pays where a kernel is bound by HBM traffic: the front pass, and
+// sweep passes of at most 4 sweeps.  Deeper sweep passes are bound by
+// issue, and keep the narrowest halo (k columns on each side).
+constexpr bool front_aligned() { return true; }
+constexpr bool stream_aligned(int k) { return k <= 4; }
+constexpr int stream_halo(int k) { return stream_aligned(k) ? 16 : k; }
+template <int RX>
+constexpr int stream_width(int k) { return stream_aligned(k) ? RX - 32 : RX - 2 * k; }
+
 namespace batch2d {
 constexpr int STRIP = 256;                                    // threads (columns) per strip
-inline int front_width() { return STRIP - 1 - 2; }            // no current: halo 1 left, 2 right
-inline int sweep_width(int k) { return STRIP - 2 * k; }
+inline int front_width() { return STRIP - 32; }   // aligned front strips
+inline int sweep_width(int k) { return stream_width<STRIP>(k); }
 template <typename T>
 hipError_t launch_front(const GridDesc<T> *d, int ng, const int *items, int nitems, int L, int bin, hipStream_t s);
 template <typename T>
