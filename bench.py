@@ -154,13 +154,21 @@ def main():
     bytes_per_launch = sw["bytes"] / nl
     achieved = bytes_per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
     k = g32.block_sweeps_per_pass[0]
+    # pass depths of a fixed count: the fewest passes, deeper ones last
+    depths, rem = [], w.sweeps
+    while rem > 0:
+        kk = rem // -(-rem // k)
+        depths.append(kk)
+        rem -= kk
+    store = depths[:-1]
     traffic = profsum.traffic_per_launch(PROFILE_SUMMARY)
     # FP32 flops of one sweep of the implemented stencils (an FMA counts 2):
     # TE 18 per cell (Ex 9, Ey 9), TM 15 per cell
-    flops_per_launch = 33.0 * ncell * k
+    flops_per_launch = 33.0 * ncell * sum(store) / max(len(store), 1)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": f"k2_stream<float,3,{k}> row-streaming pass of {k} sweeps storing its iterate",
+                "kernel": f"k2_stream<float,3,K> row-streaming sweep passes storing their iterate "
+                          f"(K = {'+'.join(map(str, store))}; final pass K = {depths[-1]} adds into E)",
                 "bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_s * 1e6, 2), "launches": nl,
                 "valu_tflops": round(flops_per_launch / avg_s / 1e12, 2) if avg_s > 0 else None,
                 "valu_peak_tflops": VALU_FP32_PEAK_TFLOPS,

@@ -91,9 +91,10 @@ typedef struct mx_config {
                              delta form 6, 3; per block TE 10 (FP32), 5 (FP64),
                              delta 9, 4; TM 16 (FP32), 8 (FP64).  LDS tile: <= 8.
                              3D: 0 or 1. */
-    int variant;          /* 2D sweep kernel: 0 library choice (2), 1 LDS tile (both
-                             blocks per pass), 2 row streaming (both blocks per
-                             pass), 3 row streaming (each block on its own) */
+    int variant;          /* 2D sweep kernel: 0 library choice (FP32: 2, FP64: 3),
+                             1 LDS tile (both blocks per pass), 2 row streaming
+                             (both blocks per pass), 3 row streaming (each block
+                             on its own) */
 } mx_config;
 
 typedef struct mx_step_stats {
@@ -150,8 +151,9 @@ int mx_set_step(mx_grid *g, int64_t n);
 /* Sweeps fused per HBM pass in use (the library's or the configured choice):
    that of the TE block when it is active, else that of TM.  With a fixed m
    a block's m sweeps run in the fewest passes of at most this depth, of
-   nearly equal depth; under a tolerance the stop test follows every pass,
-   and both 2D blocks then use one depth unless sweeps_per_pass is capped. */
+   nearly equal depth, the deeper ones last; under a tolerance the stop
+   test follows every pass, and both 2D blocks then use one depth unless
+   sweeps_per_pass is capped. */
 int mx_get_sweeps_per_pass(mx_grid *g, int *k);
 
 /* Sweeps per pass of each 2D block: k[0] TE, k[1] TM (3D: k[0]). */

@@ -67,8 +67,19 @@ struct alignas(2 * sizeof(T)) Pair {
 template <typename T, int BLK, int K>
 constexpr int stream_pf() { return 2; }
 
-// components a block set carries (TE: Ex, Ey; TM: Ez)
-constexpr int stream_nc(int blk) { return ((blk & 1) ? 2 : 0) + ((blk & 2) ? 1 : 0); }
+// both blocks: one 16- or 32-byte record per column, (Ey, Ez) first so that
+// the right neighbour's pair is one aligned 8- or 16-byte read
+template <typename T>
+struct alignas(4 * sizeof(T)) Quad {
+    T ey, ez, ex, pad;
+};
+template <typename T>
+struct alignas(4 * sizeof(T)) Triple {
+    T ey, ez, ex;
+};
+
+// LDS words per column and level: TE 2, TM 1, both 4 (a padded record)
+constexpr int stream_nc(int blk) { return blk == 3 ? 4 : blk == 1 ? 2 : 1; }
 
 // LDS a tile needs: one double-buffered row of each carried component per level
 template <typename T, int BLK, int K, int RX>
@@ -86,8 +97,10 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
     static_assert(H >= K && RX - H - W >= K, "the halo must cover every level");
     constexpr int PAD = RX + 2;
     // column j of a level row sits at index j + 1 - (strip origin - K)
-    Pair<T>(*xp)[2][PAD] = reinterpret_cast<Pair<T>(*)[2][PAD]>(lds);
-    T(*xz)[2][PAD] = reinterpret_cast<T(*)[2][PAD]>((char *)lds + (TE ? sizeof(Pair<T>) * K * 2 * PAD : 0));
+    constexpr bool BOTH = TE && TM;
+    Pair<T>(*xp)[2][PAD] = reinterpret_cast<Pair<T>(*)[2][PAD]>(lds);     // TE only
+    T(*xz)[2][PAD] = reinterpret_cast<T(*)[2][PAD]>(lds);                 // TM only
+    Quad<T>(*xq)[2][PAD] = reinterpret_cast<Quad<T>(*)[2][PAD]>(lds);     // both
 
     const int sx = wid % nsx, sy = wid / nsx;
 
@@ -186,19 +199,29 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
             // arrival of row t-2l+1 of level l-1 (computed at the previous step)
             const int rho = t - 2 * l + 1;
             if (ALL || (rho >= Y0 - K + (l - 1) && rho < Y0 + L + K - (l - 1))) {
-                if (TE) {
+                T exm, eym, eyp, ezm, ezp;
+                if (BOTH) {
+                    const Quad<T> qm = xq[l - 1][pr][i];                                   // column - 1
+                    const Pair<T> qp = *reinterpret_cast<const Pair<T> *>(&xq[l - 1][pr][i + 2]);  // (Ey, Ez), column + 1
+                    exm = qm.ex; eym = qm.ey; ezm = qm.ez; eyp = qp.x; ezp = qp.y;
+                } else if (TE) {
                     const Pair<T> pm = xp[l - 1][pr][i];       // column - 1
                     const Pair<T> pp = xp[l - 1][pr][i + 2];   // column + 1
+                    exm = pm.x; eym = pm.y; eyp = pp.y; ezm = ezp = T(0);
+                } else {
+                    ezp = xz[l - 1][pr][i + 2]; ezm = xz[l - 1][pr][i];
+                    exm = eym = eyp = T(0);
+                }
+                if (TE) {
                     const T exn = out[l - 1][0], eyn = out[l - 1][1];
                     wex[l][0] = wex[l][1]; wex[l][1] = wex[l][2]; wex[l][2] = exn;
-                    wg[l][0] = wg[l][1]; wg[l][1] = wg[l][2]; wg[l][2] = pp.y - eyn;
-                    wley[l][0] = wley[l][1]; wley[l][1] = d2(pm.y, eyn, pp.y);
-                    wh[l][0] = wh[l][1]; wh[l][1] = exn - pm.x;
+                    wg[l][0] = wg[l][1]; wg[l][1] = wg[l][2]; wg[l][2] = eyp - eyn;
+                    wley[l][0] = wley[l][1]; wley[l][1] = d2(eym, eyn, eyp);
+                    wh[l][0] = wh[l][1]; wh[l][1] = exn - exm;
                     wey[l][0] = wey[l][1]; wey[l][1] = eyn;
                 }
                 if (TM) {
                     const T ezn = out[l - 1][2];
-                    const T ezp = xz[l - 1][pr][i + 2], ezm = xz[l - 1][pr][i];
                     wez[l][0] = wez[l][1]; wez[l][1] = wez[l][2]; wez[l][2] = ezn;
                     wlx[l][0] = wlx[l][1]; wlx[l][1] = wlx[l][2]; wlx[l][2] = d2(ezm, ezn, ezp);
                 }
@@ -242,8 +265,9 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
                         out[l][q] = nv[q];
                         wc[l][0][q] = nc[q];   // carried value of this row, read by level l+1 next step
                     }
-                    if (TE) xp[l][pw][i + 1] = Pair<T>{nv[0], nv[1]};
-                    if (TM) xz[l][pw][i + 1] = nv[2];
+                    if (BOTH) *reinterpret_cast<Triple<T> *>(&xq[l][pw][i + 1]) = Triple<T>{nv[1], nv[2], nv[0]};
+                    else if (TE) xp[l][pw][i + 1] = Pair<T>{nv[0], nv[1]};
+                    else xz[l][pw][i + 1] = nv[2];
                 } else if (outcol && (ALL ? r < rend : (r >= Y0 && r < rend))) {
                     // (in the steady state r >= Y0 holds: t >= Y0 + 2K)
                     const unsigned o = (unsigned)(r * nx + gxi) * (unsigned)sizeof(T);
@@ -278,8 +302,9 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
                 out[0][q] = px[ps][q];
                 wc[0][0][q] = pc[ps][q];
             }
-            if (TE) xp[0][pw][i + 1] = Pair<T>{px[ps][0], px[ps][1]};
-            if (TM) xz[0][pw][i + 1] = px[ps][2];
+            if (BOTH) *reinterpret_cast<Triple<T> *>(&xq[0][pw][i + 1]) = Triple<T>{px[ps][1], px[ps][2], px[ps][0]};
+            else if (TE) xp[0][pw][i + 1] = Pair<T>{px[ps][0], px[ps][1]};
+            else xz[0][pw][i + 1] = px[ps][2];
             // shift; the tail receives row t+PF (in the unrolled body
             // unconditionally: a row past the end is a valid, unused row)
 #pragma unroll

@@ -285,7 +285,10 @@ int mx_init(const mx_config *cfg, void *stream, void *workspace, size_t workspac
     g->step = 0;
     g->bound = false;
     g->has_j = false;
-    g->variant = cfg->variant > 0 ? cfg->variant : 2;
+    // library choice: FP32 runs both blocks in one pass (7 sweeps deep);
+    // FP64, whose joint passes are only 3 deep, runs each block on its own
+    // (TE 5, TM 8 deep), which moves fewer bytes per step
+    g->variant = cfg->variant > 0 ? cfg->variant : (cfg->dtype == MX_F64 ? 3 : 2);
     pass_depths(cfg, g->variant, g->spp);
     const size_t arr = up((size_t)g->ncell * elem_of(cfg));
     char *p = g->ws;
@@ -417,7 +420,8 @@ int block_mask_comps(int ndim, int b) { return ndim == 3 ? 7 : (b == 0 ? 3 : 4);
 // passes of each block on its own (groups {TE}, {TM}); the LDS-tile kernel
 // and 3D run all blocks together (one group).  With a fixed count, a group's
 // m sweeps are cut into the fewest passes of at most spp sweeps, of nearly
-// equal depth; under a tolerance every pass but the last is spp deep.
+// equal depth (deeper ones last); under a tolerance every pass but the last
+// is spp deep.
 template <typename T>
 int run_sweeps(mx_grid *g, void *const rhs[3], const int *target_in, bool tolmode, const double *rhsn,
                void *E_fuse[3], bool e_done[2], const T **res, mx_step_stats *st)
@@ -448,7 +452,9 @@ int run_sweeps(mx_grid *g, void *const rhs[3], const int *target_in, bool tolmod
                 }
             if (!act) break;
             const int spp = (act & 1) ? g->spp[0] : g->spp[1];
-            const int kk = tolmode ? std::min(rem, spp) : (rem + (rem + spp - 1) / spp - 1) / ((rem + spp - 1) / spp);
+            // fixed count: the fewest passes, the deeper ones last (the final
+            // pass also reads and writes E, so its sweeps are the cheapest)
+            const int kk = tolmode ? std::min(rem, spp) : rem / ((rem + spp - 1) / spp);
             const bool first = (act & 1) ? done[0] == 0 : done[1] == 0;
             // E += x fused into this pass when every active block of the group ends here
             bool fin = !tolmode && E_fuse != nullptr;

@@ -87,11 +87,13 @@ def summarize(trace, fetch, write, copy_bytes, bench_json, kernel_re, out, cmds)
     L.append("")
     L.append("| kernel | calls | avg us | total ms | % |")
     L.append("|---|---:|---:|---:|---:|")
-    sel = None
+    sel_calls, sel_total, sel_names = 0, 0.0, []
     for n, c, tot, avg, pct in st:
         L.append(f"| {_short(n)} | {c} | {avg:.1f} | {tot / 1e3:.2f} | {pct:.1f} |")
-        if sel is None and re.search(kernel_re, n):
-            sel = (n, c, avg)
+        if re.search(kernel_re, n):
+            sel_calls += c
+            sel_total += tot
+            sel_names.append(_short(n))
     L.append("")
     if bench:
         L.append("library HIP-event averages inside the timed region of the same command (bench.py output):")
@@ -112,25 +114,27 @@ def summarize(trace, fetch, write, copy_bytes, bench_json, kernel_re, out, cmds)
     L.append("")
     L.append("| kernel | dispatches | read MB | written MB | traffic MB |")
     L.append("|---|---:|---:|---:|---:|")
-    chosen = None
+    sel_rd, sel_wr = [], []
     for k in sorted(f, key=lambda k: -statistics.mean(f[k])):
         if k == ck or k not in w:
             continue
         rd = statistics.mean(f[k]) * ff
         wr = statistics.mean(w[k]) * fw
         L.append(f"| {_short(k)} | {len(f[k])} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | {(rd + wr) / 1e6:.1f} |")
-        if chosen is None and re.search(kernel_re, k):
-            chosen = (k, rd, wr)
+        if re.search(kernel_re, k):
+            sel_rd += [v * ff for v in f[k]]
+            sel_wr += [v * fw for v in w[k]]
     L.append("")
-    if sel is None or chosen is None:
+    if not sel_calls or not sel_rd:
         raise SystemExit(f"kernel /{kernel_re}/ not found in the runs")
-    L.append(f"dominant kernel: `{_short(sel[0])}`, {sel[1]} calls, rocprofv3 average {sel[2]:.1f} us")
+    L.append(f"dominant kernel: {', '.join('`' + n + '`' for n in sel_names)} (one category: the sweep passes "
+             f"that store their iterate), {sel_calls} calls, rocprofv3 average {sel_total / sel_calls:.1f} us")
     if bench:
         r = bench["roofline"]
         L.append(f"bench.py HIP-event average of the same launches: {r['avg_launch_us']} us, "
                  f"algorithmic {r['bytes_per_launch'] / 1e6:.1f} MB per launch ({r['achieved']} GB/s)")
     L.append("")
-    L.append(f"traffic_bytes_per_launch: {chosen[1] + chosen[2]:.0f}")
+    L.append(f"traffic_bytes_per_launch: {statistics.mean(sel_rd) + statistics.mean(sel_wr):.0f}")
     L.append(f"source_sha256: {source_sha()}")
     open(out, "w").write("\n".join(L) + "\n")
     return out
