@@ -55,6 +55,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run 4 plain device copies of this many bytes (counter calibration)")
+    ap.add_argument("--workload", default="modes2d",
+                    choices=["modes2d", "planewave_te", "planewave_3d", "batch", "adjoint"],
+                    help="modes2d (default): the 4096^2 line above; the others time the 128^2 TE "
+                         "tolerance solve, the 512^3 3D solve, the 64-grid batch and the adjoint")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -73,6 +77,12 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(3)
+
+    if args.workload != "modes2d":
+        steps = args.steps if "--steps" in sys.argv else None
+        warm = args.warmup if "--warmup" in sys.argv else None
+        print(json.dumps(OTHER_WORKLOADS[args.workload](steps, warm)), flush=True)
+        return
 
     if args.copy_probe > 0:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
@@ -216,6 +226,161 @@ def main():
     }
     g32.close()
     print(json.dumps(out), flush=True)
+
+
+# --------------------------------------------------------------------------
+# The other workloads (not the headline line): each prints one JSON object
+# --------------------------------------------------------------------------
+
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _line(name, value, unit, extra):
+    out = {"metric": "Gcell-steps/s incl. mass-matrix sweeps" if unit == "Gcell-steps/s" else name,
+           "value": round(value, 4), "unit": unit, "n_gpus": 1, "data": "synthetic", "workload": name}
+    out.update(extra)
+    return out
+
+
+def bench_planewave_te(steps, warm):
+    """128^2 TE plane wave + noise, FP64, solve to 1e-12 (checked every pass)."""
+    import torch
+    from paper_1907_13088_amd import inputs as I
+    from paper_1907_13088_amd import mx
+    steps = steps or 200
+    w = I.planewave_te_2d(steps=steps)
+    cfg = mx.make_config(2, w.shape[::-1], w.dt, w.d, "f64", w.blocks, w.sweeps, w.tol, 0)
+    g = mx.Grid(cfg)
+    E = [torch.tensor(a, device="cuda") for a in w.E]
+    B = [torch.tensor(a, device="cuda") for a in w.B]
+    g.bind(E, B)
+    g.step(warm or 5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = g.step(steps, stats=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sweeps = sum(s.sweeps[0] for s in st) / steps
+    return _line("128x128 TE plane wave, FP64, tol 1e-12", w.cells * steps / dt / 1e9, "Gcell-steps/s",
+                 {"steps": steps, "us_per_step": round(dt / steps * 1e6, 1), "mean_sweeps": round(sweeps, 1),
+                  "sweeps_per_pass": g.sweeps_per_pass, "dtype": "f64",
+                  "note": "latency bound: the stop test synchronises with the host after every pass"})
+
+
+def bench_planewave_3d(steps, warm):
+    """512^3, FP32, all six components, tol 1e-7 (delta form)."""
+    import torch
+    from paper_1907_13088_amd import inputs as I
+    from paper_1907_13088_amd import mx
+    steps = steps or 5
+    warm = 1 if warm is None else warm
+    t0 = time.time()
+    w = I.planewave_3d(steps=steps + warm)
+    log(f"3D inputs generated in {time.time() - t0:.1f}s")
+    cfg = mx.make_config(3, w.shape[::-1], w.dt, w.d, "f32", 3, w.sweeps, w.tol, w.filter_passes,
+                         form=mx.FORM_DELTA)
+    g = mx.Grid(cfg)
+    E = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in w.E]
+    B = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in w.B]
+    J = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in w.J0]
+    del w.E, w.B, w.J0
+    g.bind(E, B)
+    g.set_current(J)
+    env = [float(x) for x in w.env]
+    if warm:
+        g.step(warm, env[:warm])
+    torch.cuda.synchronize()
+    g.profile_enable(True)
+    t0 = time.perf_counter()
+    st = g.step(steps, env[warm:warm + steps], stats=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = g.profile_read()
+    sw = prof["sweep"]
+    sweeps = sum(s.sweeps[0] for s in st) / steps
+    return _line("512^3 plane wave + 32 pulses, FP32, tol 1e-7", w.cells * steps / dt / 1e9, "Gcell-steps/s",
+                 {"steps": steps, "ms_per_step": round(dt / steps * 1e3, 2), "mean_sweeps": round(sweeps, 1),
+                  "dtype": "f32", "nonconverged_steps": sum(s.nonconverged[0] for s in st),
+                  "sweep_pass_us": round(1e3 * sw["ms"] / max(sw["launches"], 1), 1),
+                  "sweep_pass_GBps": round(sw["bytes"] / (sw["ms"] / 1e3) / 1e9, 1) if sw["ms"] else None})
+
+
+def bench_batch(steps, warm):
+    """64 grids of uneven size and Courant number, FP32, m = 20, one persistent launch."""
+    import torch
+    from paper_1907_13088_amd import inputs as I
+    from paper_1907_13088_amd import mx
+    steps = steps or 500
+    t0 = time.time()
+    ws = I.batch_2d(steps=steps)
+    log(f"batch inputs generated in {time.time() - t0:.1f}s")
+    cells = sum(w.cells for w in ws)
+    res = {}
+    for persistent in (True, False):
+        cfgs = [mx.make_config(2, w.shape[::-1], w.dt, (1.0, 1.0), "f32", mx.MX_ALL, w.sweeps, 0.0, 0)
+                for w in ws]
+        b = mx.Batch(cfgs)
+        for gi, w in enumerate(ws):
+            b.bind(gi, [torch.tensor(a, dtype=torch.float32, device="cuda") for a in w.E],
+                   [torch.tensor(a, dtype=torch.float32, device="cuda") for a in w.B])
+        b.step(warm or 2, persistent=persistent)
+        torch.cuda.synchronize()
+        s0, s1 = _events()
+        s0.record()
+        b.step(steps, persistent=persistent)
+        s1.record()
+        torch.cuda.synchronize()
+        ms = s0.elapsed_time(s1)
+        res["persistent" if persistent else "grouped"] = {"Gcell_steps_per_s": round(cells * steps / ms / 1e6, 3),
+                                                          "ms": round(ms, 1), "plan": b.plan()}
+        b.close()
+    return _line("64 batched 2D grids, FP32, m = 20", res["persistent"]["Gcell_steps_per_s"], "Gcell-steps/s",
+                 {"steps": steps, "cells": cells, "dtype": "f32", "schedules": res})
+
+
+def bench_adjoint(steps, warm):
+    """2048^2 FP32, 256 learnable sources, forward + backward with checkpoints every 50 steps."""
+    import math
+    import numpy as np
+    import torch
+    from paper_1907_13088_amd import inputs as I
+    from paper_1907_13088_amd import mx
+    from paper_1907_13088_amd.adjoint import SourceSet, field_steps
+    n, nsrc, steps = 2048, 256, steps or 500
+    w = I.modes_2d((n, n), nmodes=64, npulses=0, steps=steps, seed=1005, dtype="f32")
+    origins, shapes, amps = I.adjoint_sources_2d(n=n, nsrc=nsrc, seed=1005)
+    shapes = np.asarray(I.round_to(np.float32, shapes))
+    amps = np.asarray(I.round_to(np.float32, amps))
+    env = [math.sin(0.3 * (s + 0.5) * w.dt) for s in range(steps)]
+    cfg = mx.make_config(2, (n, n), w.dt, (1.0, 1.0), "f32", mx.MX_ALL, 20, 0.0, 3)
+    g = mx.Grid(cfg)
+    src = SourceSet(torch.tensor(origins, device="cuda"), torch.tensor(shapes, dtype=torch.float32, device="cuda"))
+    a = torch.tensor(amps, device="cuda", requires_grad=True)
+    E0 = [torch.tensor(x, dtype=torch.float32, device="cuda", requires_grad=True) for x in w.E]
+    B0 = [torch.tensor(x, dtype=torch.float32, device="cuda", requires_grad=True) for x in w.B]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E, B = field_steps(a, E0, B0, g, src, env, steps, checkpoint_every=50, verify=False)
+    c0 = n // 2 - 32
+    L = (E[2][c0:c0 + 64, c0:c0 + 64] ** 2).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    cells = n * n
+    return _line("2048^2 adjoint, 256 sources, FP32, 500 steps", cells * steps / (t2 - t0) / 1e9, "Gcell-steps/s",
+                 {"steps": steps, "dtype": "f32", "forward_s": round(t1 - t0, 3), "backward_s": round(t2 - t1, 3),
+                  "forward_Gcell_steps_per_s": round(cells * steps / (t1 - t0) / 1e9, 3),
+                  "backward_Gcell_steps_per_s": round(cells * steps / (t2 - t1) / 1e9, 3),
+                  "note": "value counts forward and backward (recompute of every checkpoint segment, "
+                          "transposed steps, source projection) over the same steps"})
+
+
+OTHER_WORKLOADS = {"planewave_te": bench_planewave_te, "planewave_3d": bench_planewave_3d,
+                   "batch": bench_batch, "adjoint": bench_adjoint}
 
 
 if __name__ == "__main__":

@@ -221,11 +221,15 @@ int mx_sources_project(mx_grid *g, int nsrc, int W, const int64_t *origins, cons
  * dt and coefficients; TE+TM; no current; one fixed m >= 1 for all grids;
  * one dtype).  Every phase of a step of all grids is one launch over the
  * concatenated work items of the batch; with persistent = 1 all nsteps
- * steps of all grids run inside a single cooperative launch, phases
- * separated by grid-wide barriers whose wait is bounded (a time-out returns
- * MX_EDEVICE).  mx_batch_init with sweeps_per_pass = 0 times candidate
- * schedules on workspace scratch fields (the bound state is never touched)
- * and keeps the fastest.  The workspace holds 15 arrays per grid.
+ * steps of all grids run inside a single cooperative launch, in which
+ * workgroups claim the work items of each phase from an atomic counter;
+ * phases are separated by grid-wide barriers whose wait is bounded (a
+ * time-out returns MX_EDEVICE).  Passes are at most sweeps_per_pass of the
+ * first config deep (capped at 7); mx_batch_init with sweeps_per_pass = 0
+ * times candidate pass depths and chunk lengths on workspace scratch
+ * fields (the bound state is never touched), separately for the grouped
+ * and the persistent schedule, and keeps the fastest of each.  The
+ * workspace holds 15 arrays per grid.
  * ------------------------------------------------------------------------ */
 typedef struct mx_batch mx_batch;
 
@@ -234,9 +238,9 @@ int mx_batch_init(const mx_config *cfgs, int ngrids, void *stream, void *workspa
                   size_t workspace_bytes, mx_batch **out);
 int mx_batch_bind(mx_batch *b, int grid, void *const E[3], void *const B[3]);
 int mx_batch_step(mx_batch *b, int nsteps, int persistent);
-/* The schedule in use: sweeps per pass (tuned at init when the configs ask
-   for sweeps_per_pass = 0), total work items of one step, and the
-   workgroups of the persistent launch. */
+/* The schedules in use: sweeps per pass of the grouped schedule (tuned at
+   init when the configs ask for sweeps_per_pass = 0), its total work items
+   of one step, and the workgroups of the persistent launch. */
 int mx_batch_get_plan(mx_batch *b, int *sweeps_per_pass, int *tiles_total, int *persistent_blocks);
 int mx_batch_destroy(mx_batch *b);
 

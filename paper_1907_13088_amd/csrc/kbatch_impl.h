@@ -7,10 +7,11 @@
 // items[g+1].  Two schedules:
 //  * grouped: one launch per phase (front, then each sweep pass) covering
 //    the items of every grid;
-//  * persistent: one cooperative launch runs all steps; workgroups stride
-//    over the items of each phase and meet at a grid-wide barrier between
-//    phases.  The barrier's wait is bounded: on time-out it raises an error
-//    flag and every workgroup leaves, so the launch always drains.
+//  * persistent: one cooperative launch runs all steps; workgroups claim the
+//    items of each phase from an atomic counter (so uneven items balance)
+//    and meet at a grid-wide barrier between phases.  The barrier's wait is
+//    bounded: on time-out it raises an error flag and every workgroup
+//    leaves, so the launch always drains.
 #pragma once
 
 #include "k2f_impl.h"
@@ -19,7 +20,7 @@
 namespace mx {
 namespace batch2d {
 
-constexpr int RX = 256;
+constexpr int RX = STRIP;
 
 // largest g with items[g] <= it, items[0] = 0, items[ng] = total
 __device__ __forceinline__ int find_grid(const int *items, int ng, int it)
@@ -48,7 +49,7 @@ __device__ __forceinline__ void front_item(const GridDesc<T> *d, int ng, const i
     fa.env_src = T(0);
     fa.partial = nullptr;
     front2d::front_tile<T, 3, 0, RX, false>(gd.c, fa, gd.B[bin][0], gd.B[bin][1], gd.B[bin][2], L, gd.nsx_f,
-                                     it - items[g], 0, lds, sred);
+                                            it - items[g], 0, lds, sred);
 }
 
 template <typename T, int K, int OM>
@@ -88,70 +89,184 @@ __global__ __launch_bounds__(RX) void kb_sweep(const GridDesc<T> *d, int ng, con
     sweep_item<T, K, OM>(d, ng, items, L, first != 0, xin, xout, blockIdx.x, lds, sred);
 }
 
-// Grid-wide barrier for a cooperative launch.  All threads fence their
-// global writes at device scope (other XCDs' L2s must see them), thread 0
-// arrives on a counter and waits for the generation to move; the wait is
-// bounded.  Returns false (every thread) after a time-out.
+// Grid-wide barrier for a cooperative launch.  bar[0] counts arrivals,
+// bar[1] is the generation, bar[2] the work counter of the phase that ends
+// here: the last workgroup to arrive resets it for the next phase before it
+// releases the others.  Every wave first waits for its own memory
+// operations; then one thread per workgroup makes the workgroup's writes
+// visible at device scope (other XCDs have their own L2), arrives, polls
+// the generation with plain device-scope loads (no cache invalidation per
+// poll, which would evict the data of workgroups still computing on the
+// same XCD), and acquires once.  The wait is bounded; returns false (every
+// thread) after a time-out.
 __device__ __forceinline__ bool grid_barrier(unsigned *bar, unsigned nblocks, int *err, int *sflag)
 {
-    __threadfence();
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's loads and stores have completed
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
-        const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned prev = atomicAdd(&bar[0], 1u);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned prev = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (prev == nblocks - 1) {
-            atomicExch(&bar[0], 0u);
-            __threadfence();
-            atomicAdd(&bar[1], 1u);
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bar[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             unsigned spins = 0;
-            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
                 __builtin_amdgcn_s_sleep(2);
                 if (++spins > (1u << 25)) {   // about two seconds
-                    atomicOr(err, 1);
+                    __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     ok = 0;
                     break;
                 }
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
         *sflag = ok;
     }
     __syncthreads();
-    const bool ok = *sflag != 0;
-    __threadfence();
-    return ok;
+    return *sflag != 0;
+}
+
+// Claim items [0, n) one at a time from the phase's work counter.
+template <typename F>
+__device__ __forceinline__ void claim_items(unsigned *work, int n, int *s_it, F &&f)
+{
+    for (;;) {
+        if (threadIdx.x == 0) *s_it = (int)atomicAdd(work, 1u);
+        __syncthreads();
+        const int it = *s_it;
+        __syncthreads();   // every thread has read the claim before the next one
+        if (it >= n) break;
+        f(it);
+    }
 }
 
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 
-// All nsteps steps of all grids in one launch; passes of exactly Q sweeps
-// (m = npass * Q).
+// All nsteps steps of all grids in one launch; npass passes per step, the
+// first nlow of Q - 1 sweeps, the others of Q.
 template <typename T, int Q>
 __global__ __launch_bounds__(RX) void kb_persistent(const GridDesc<T> *d, int ng, const int *items_f,
                                                     const int *items_s, int Lf, int Ls, int nsteps, int npass,
-                                                    int bin0, unsigned *bar, int *err)
+                                                    int nlow, int bin0, unsigned *bar, int *err)
 {
     __shared__ __attribute__((aligned(16)))
         char lds[cmax(front2d::front_lds_bytes<T, 0, RX>(), stream2d::stream_lds_bytes<T, 3, Q, RX>())];
     __shared__ double sred[2 * RX / 64];
-    __shared__ int sflag;
+    __shared__ int sflag, s_it;
     const int nf = items_f[ng], ns = items_s[ng];
+    unsigned *work = &bar[2];
     int bin = bin0;
     for (int step = 0; step < nsteps; step++) {
-        for (int it = blockIdx.x; it < nf; it += gridDim.x) front_item<T>(d, ng, items_f, Lf, bin, it, lds, sred);
+        claim_items(work, nf, &s_it, [&](int it) { front_item<T>(d, ng, items_f, Lf, bin, it, lds, sred); });
         bin ^= 1;
         if (!grid_barrier(bar, gridDim.x, err, &sflag)) return;
         for (int p = 0; p < npass; p++) {
             const bool first = p == 0, last = p == npass - 1;
             const int xin = (p + 1) & 1, xout = p & 1;
-            for (int it = blockIdx.x; it < ns; it += gridDim.x) {
+            const bool low = p < nlow;
+            claim_items(work, ns, &s_it, [&](int it) {
+                if constexpr (Q > 1) {
+                    if (low) {
+                        if (last)
+                            sweep_item<T, Q - 1, stream2d::OM_LAST>(d, ng, items_s, Ls, first, xin, xout, it, lds,
+                                                                    sred);
+                        else
+                            sweep_item<T, Q - 1, stream2d::OM_STORE>(d, ng, items_s, Ls, first, xin, xout, it, lds,
+                                                                     sred);
+                        return;
+                    }
+                }
                 if (last) sweep_item<T, Q, stream2d::OM_LAST>(d, ng, items_s, Ls, first, xin, xout, it, lds, sred);
                 else sweep_item<T, Q, stream2d::OM_STORE>(d, ng, items_s, Ls, first, xin, xout, it, lds, sred);
-            }
+            });
             if (!grid_barrier(bar, gridDim.x, err, &sflag)) return;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers (instantiated per element type in kbatch_f32.hip, kbatch_f64.hip)
+// ---------------------------------------------------------------------------
+
+template <typename T>
+hipError_t launch_front_impl(const GridDesc<T> *d, int ng, const int *items, int nitems, int L, int bin,
+                             hipStream_t s)
+{
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL((kb_front<T>), dim3(nitems), dim3(RX), 0, s, d, ng, items, L, bin);
+    return hipGetLastError();
+}
+
+template <typename T, int K>
+hipError_t sweep_disp(const GridDesc<T> *d, int ng, const int *items, int nitems, int L, int k, bool first,
+                      bool last, int xin, int xout, hipStream_t s)
+{
+    if constexpr (K == 0) {
+        return hipErrorInvalidValue;
+    } else {
+        if (k != K) return sweep_disp<T, K - 1>(d, ng, items, nitems, L, k, first, last, xin, xout, s);
+        if (last)
+            hipLaunchKernelGGL((kb_sweep<T, K, stream2d::OM_LAST>), dim3(nitems), dim3(RX), 0, s, d, ng, items, L,
+                               (int)first, xin, xout);
+        else
+            hipLaunchKernelGGL((kb_sweep<T, K, stream2d::OM_STORE>), dim3(nitems), dim3(RX), 0, s, d, ng, items, L,
+                               (int)first, xin, xout);
+        return hipGetLastError();
+    }
+}
+
+template <typename T>
+hipError_t launch_sweep_impl(const GridDesc<T> *d, int ng, const int *items, int nitems, int L, int k, bool first,
+                             bool last, int xin, int xout, hipStream_t s)
+{
+    if (nitems <= 0) return hipSuccess;
+    return sweep_disp<T, KMAX>(d, ng, items, nitems, L, k, first, last, xin, xout, s);
+}
+
+template <typename T, int Q>
+int occ_q()
+{
+    static int n = -1;
+    if (n < 0) {
+        int o = 0, dev = 0, cu = 0;
+        (void)hipGetDevice(&dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, kb_persistent<T, Q>, RX, 0) != hipSuccess) o = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cu = 0;
+        n = o * cu;
+    }
+    return n;
+}
+
+template <typename T, int Q>
+int persistent_blocks_disp(int q)
+{
+    if constexpr (Q == 0) {
+        return 0;
+    } else {
+        if (q == Q) return occ_q<T, Q>();
+        return persistent_blocks_disp<T, Q - 1>(q);
+    }
+}
+
+template <typename T, int Q>
+hipError_t persist_disp(const GridDesc<T> *d, int ng, const int *items_f, const int *items_s, int Lf, int Ls,
+                        int nsteps, int q, int npass, int nlow, int bin0, unsigned *bar, int *err, int nblocks,
+                        hipStream_t s)
+{
+    if constexpr (Q == 0) {
+        return hipErrorInvalidValue;
+    } else {
+        if (q != Q)
+            return persist_disp<T, Q - 1>(d, ng, items_f, items_s, Lf, Ls, nsteps, q, npass, nlow, bin0, bar, err,
+                                          nblocks, s);
+        void *args[] = {(void *)&d, (void *)&ng, (void *)&items_f, (void *)&items_s, (void *)&Lf, (void *)&Ls,
+                        (void *)&nsteps, (void *)&npass, (void *)&nlow, (void *)&bin0, (void *)&bar, (void *)&err};
+        return hipLaunchCooperativeKernel((const void *)kb_persistent<T, Q>, dim3(nblocks), dim3(RX), args, 0, s);
     }
 }
 

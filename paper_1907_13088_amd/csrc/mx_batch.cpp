@@ -84,23 +84,57 @@ struct mx_batch {
     int *items_f, *items_s;            // device prefix sums (ng + 1)
     unsigned *bar;                     // device barrier counters
     int *err;                          // device error flag
-    int spp, Lf, Ls;                   // schedule
-    int nf, ns;                        // items per phase
-    int pq;                            // persistent pass size (0: none)
+    int spp, Lf, Ls;                   // grouped schedule: pass depth cap, chunk rows
+    int pk, pLf, pLs;                  // persistent schedule: the same
+    int nf, ns;                        // items per phase (of the last upload)
     bool tuned;
 };
 
 namespace {
 
-template <typename T>
-int upload(mx_batch *b, bool scratch_fields)
+// pass sizes of one step: the fewest passes of at most k sweeps, sizes as
+// equal as possible, the deeper ones last (as the single-grid schedule)
+void pass_sizes(int m, int k, std::vector<int> &sz)
 {
-    // Descriptors and item tables for the current schedule.  With
-    // scratch_fields the E and B of every grid point at workspace arrays (the
-    // autotuner's trial steps never touch the caller's state).
+    sz.clear();
+    const int np = (m + k - 1) / k;
+    const int q = m / np, r = m % np;
+    for (int p = 0; p < np; p++) sz.push_back(p >= np - r ? q + 1 : q);
+}
+
+// column width the sweep work items are cut with: the narrowest strip of
+// any pass depth the schedule runs (a strip of a wider pass then covers its
+// columns with room to spare; a narrower one would leave columns out)
+int cut_width(int m, int k)
+{
+    std::vector<int> sz;
+    pass_sizes(m, k, sz);
+    int w = 1 << 30;
+    for (int s : sz) w = std::min(w, batch2d::sweep_width(s));
+    return w;
+}
+
+// persistent passes: npass passes, the first nlow of q - 1 sweeps, the rest q
+void persistent_shape(int m, int k, int *q, int *npass, int *nlow)
+{
+    std::vector<int> sz;
+    pass_sizes(m, k, sz);
+    *npass = (int)sz.size();
+    *q = sz.back();
+    *nlow = 0;
+    for (int v : sz) *nlow += v < *q ? 1 : 0;
+}
+
+template <typename T>
+int upload(mx_batch *b, bool scratch_fields, int k, int Lf, int Ls)
+{
+    // Descriptors and item tables for a schedule of passes at most k deep
+    // and chunks of Lf (front) and Ls (sweeps) rows.  With scratch_fields
+    // the E and B of every grid point at workspace arrays (the autotuner's
+    // trial steps never touch the caller's state).
     std::vector<GridDesc<T>> d(b->ng);
     std::vector<int> itf(b->ng + 1, 0), its(b->ng + 1, 0);
-    const int wf = batch2d::front_width(), wsw = batch2d::sweep_width(b->spp);
+    const int wf = batch2d::front_width(), wsw = cut_width(b->m, k);
     for (int g = 0; g < b->ng; g++) {
         const mx_config &c = b->cfg[g];
         GridDesc<T> &gd = d[g];
@@ -123,8 +157,8 @@ int upload(mx_batch *b, bool scratch_fields)
         const int nx = (int)c.n[0], ny = (int)c.n[1];
         gd.nsx_f = (nx + wf - 1) / wf;
         gd.nsx_s = (nx + wsw - 1) / wsw;
-        itf[g + 1] = itf[g] + gd.nsx_f * ((ny + b->Lf - 1) / b->Lf);
-        its[g + 1] = its[g] + gd.nsx_s * ((ny + b->Ls - 1) / b->Ls);
+        itf[g + 1] = itf[g] + gd.nsx_f * ((ny + Lf - 1) / Lf);
+        its[g + 1] = its[g] + gd.nsx_s * ((ny + Ls - 1) / Ls);
     }
     b->nf = itf[b->ng];
     b->ns = its[b->ng];
@@ -133,15 +167,6 @@ int upload(mx_batch *b, bool scratch_fields)
     BCHK(hipMemcpyAsync(b->items_s, its.data(), sizeof(int) * (b->ng + 1), hipMemcpyHostToDevice, b->stream));
     BCHK(hipStreamSynchronize(b->stream));   // the host vectors go out of scope
     return MX_OK;
-}
-
-// pass sizes of one step: npass passes, sizes as equal as possible
-void pass_sizes(int m, int k, std::vector<int> &sz)
-{
-    sz.clear();
-    const int np = (m + k - 1) / k;
-    const int q = m / np, r = m % np;
-    for (int p = 0; p < np; p++) sz.push_back(p < r ? q + 1 : q);
 }
 
 template <typename T>
@@ -166,14 +191,17 @@ int grouped_steps(mx_batch *b, int nsteps, int bin0)
 template <typename T>
 int persistent_steps(mx_batch *b, int nsteps, int bin0)
 {
-    const int q = b->pq;
+    int q, npass, nlow;
+    persistent_shape(b->m, b->pk, &q, &npass, &nlow);
     const int nb = batch2d::persistent_blocks<T>(q);
-    if (q <= 0 || nb <= 0) return bfail(MX_EINVAL, "no persistent schedule for m = %d", b->m);
-    // clear the error flag with a copy (no memset node in a captured stream)
-    static const int zero = 0;
-    BCHK(hipMemcpyAsync(b->err, &zero, sizeof(int), hipMemcpyHostToDevice, b->stream));
-    BCHK(batch2d::launch_persistent<T>((const GridDesc<T> *)b->desc, b->ng, b->items_f, b->items_s, b->Lf, b->Ls,
-                                       nsteps, q, b->m / q, bin0, b->bar, b->err, nb, b->stream));
+    if (nb <= 0) return bfail(MX_EDEVICE, "no co-resident workgroups for the persistent batch kernel");
+    // barrier counters and error flag start at zero (a copy: no memset node
+    // in a captured stream)
+    static const unsigned zero[4] = {0, 0, 0, 0};
+    BCHK(hipMemcpyAsync(b->bar, zero, 3 * sizeof(unsigned), hipMemcpyHostToDevice, b->stream));
+    BCHK(hipMemcpyAsync(b->err, zero, sizeof(int), hipMemcpyHostToDevice, b->stream));
+    BCHK(batch2d::launch_persistent<T>((const GridDesc<T> *)b->desc, b->ng, b->items_f, b->items_s, b->pLf,
+                                       b->pLs, nsteps, q, npass, nlow, bin0, b->bar, b->err, nb, b->stream));
     int h = 0;
     BCHK(hipMemcpyAsync(&h, b->err, sizeof(int), hipMemcpyDeviceToHost, b->stream));
     BCHK(hipStreamSynchronize(b->stream));
@@ -181,48 +209,48 @@ int persistent_steps(mx_batch *b, int nsteps, int bin0)
     return MX_OK;
 }
 
+// Time two steps of each candidate plan (pass depth cap x chunk rows) on
+// scratch fields, for the grouped and for the persistent schedule.
 template <typename T>
-int autotune(mx_batch *b)
+int autotune(mx_batch *b, bool grouped, bool persistent)
 {
-    // time one grouped step per candidate on scratch fields
     hipEvent_t e0, e1;
     BCHK(hipEventCreate(&e0));
     BCHK(hipEventCreate(&e1));
-    int best_k = 5, best_l = 64;
-    float best = 1e30f;
-    const int ks[] = {3, 4, 5, 6, 7};
+    // FP32 passes fit two waves per SIMD up to 7 sweeps, FP64 up to 3
+    const std::vector<int> ks = sizeof(T) == 4 ? std::vector<int>{4, 5, 6, 7} : std::vector<int>{2, 3, 4};
     const int ls[] = {32, 64, 128};
-    for (int k : ks)
-        for (int l : ls) {
-            b->spp = k;
-            b->Lf = b->Ls = l;
-            int rc = upload<T>(b, true);
-            if (rc) return rc;
-            rc = grouped_steps<T>(b, 1, 0);   // warm
-            if (rc) return rc;
-            BCHK(hipEventRecord(e0, b->stream));
-            rc = grouped_steps<T>(b, 2, 0);
-            if (rc) return rc;
-            BCHK(hipEventRecord(e1, b->stream));
-            BCHK(hipEventSynchronize(e1));
-            float ms = 0.f;
-            BCHK(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) { best = ms; best_k = k; best_l = l; }
-        }
+    for (int sched = 0; sched < 2; sched++) {
+        if ((sched == 0 && !grouped) || (sched == 1 && !persistent)) continue;
+        float best = 1e30f;
+        int bk = 5, bl = 64;
+        for (int k : ks)
+            for (int l : ls) {
+                int rc = upload<T>(b, true, k, l, l);
+                if (rc) return rc;
+                const int keep[6] = {b->spp, b->Lf, b->Ls, b->pk, b->pLf, b->pLs};
+                b->spp = b->pk = k;
+                b->Lf = b->Ls = b->pLf = b->pLs = l;
+                rc = sched == 0 ? grouped_steps<T>(b, 1, 0) : persistent_steps<T>(b, 1, 0);   // warm
+                if (!rc) {
+                    BCHK(hipEventRecord(e0, b->stream));
+                    rc = sched == 0 ? grouped_steps<T>(b, 2, 0) : persistent_steps<T>(b, 2, 0);
+                    BCHK(hipEventRecord(e1, b->stream));
+                }
+                b->spp = keep[0]; b->Lf = keep[1]; b->Ls = keep[2];
+                b->pk = keep[3]; b->pLf = keep[4]; b->pLs = keep[5];
+                if (rc) return rc;
+                BCHK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                BCHK(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) { best = ms; bk = k; bl = l; }
+            }
+        if (sched == 0) { b->spp = bk; b->Lf = b->Ls = bl; }
+        else { b->pk = bk; b->pLf = b->pLs = bl; }
+    }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    b->spp = best_k;
-    b->Lf = b->Ls = best_l;
     return MX_OK;
-}
-
-// largest pass size in [1, 6] dividing m, closest to the tuned one
-int persistent_q(int m, int k)
-{
-    int q = 0;
-    for (int c = 1; c <= 6; c++)
-        if (m % c == 0 && (q == 0 || std::abs(c - k) <= std::abs(q - k))) q = c;
-    return q;
 }
 
 }  // namespace
@@ -291,15 +319,14 @@ int mx_batch_init(const mx_config *cfgs, int ngrids, void *stream, void *workspa
     b->bar = (unsigned *)p; p += up(4 * sizeof(unsigned));
     b->err = (int *)p;
     BCHK(hipMemsetAsync(b->bar, 0, 4 * sizeof(unsigned), b->stream));
-    b->spp = cfgs[0].sweeps_per_pass > 0 ? cfgs[0].sweeps_per_pass : 5;
-    b->Lf = b->Ls = 64;
+    b->spp = b->pk = cfgs[0].sweeps_per_pass > 0 ? std::min(cfgs[0].sweeps_per_pass, batch2d::KMAX) : 5;
+    b->Lf = b->Ls = b->pLf = b->pLs = 64;
     b->tuned = false;
     if (cfgs[0].sweeps_per_pass == 0) {
-        rc = b->dtype == MX_F64 ? autotune<double>(b) : autotune<float>(b);
+        rc = b->dtype == MX_F64 ? autotune<double>(b, true, true) : autotune<float>(b, true, true);
         if (rc) { delete b; return rc; }
         b->tuned = true;
     }
-    b->pq = persistent_q(b->m, b->spp);
     *out = b;
     return MX_OK;
 }
@@ -325,17 +352,13 @@ int mx_batch_step(mx_batch *b, int nsteps, int persistent)
     if (nsteps == 0) return MX_OK;
     BCHK(hipSetDevice(b->device));
     const bool f64 = b->dtype == MX_F64;
-    int rc = f64 ? upload<double>(b, false) : upload<float>(b, false);
-    if (rc) return rc;
+    int rc;
     if (persistent) {
-        // persistent passes all have q sweeps: swap in the item table for q
-        const int keep = b->spp;
-        b->spp = b->pq;
-        rc = f64 ? upload<double>(b, false) : upload<float>(b, false);
+        rc = f64 ? upload<double>(b, false, b->pk, b->pLf, b->pLs) : upload<float>(b, false, b->pk, b->pLf, b->pLs);
         if (!rc) rc = f64 ? persistent_steps<double>(b, nsteps, 0) : persistent_steps<float>(b, nsteps, 0);
-        b->spp = keep;
     } else {
-        rc = f64 ? grouped_steps<double>(b, nsteps, 0) : grouped_steps<float>(b, nsteps, 0);
+        rc = f64 ? upload<double>(b, false, b->spp, b->Lf, b->Ls) : upload<float>(b, false, b->spp, b->Lf, b->Ls);
+        if (!rc) rc = f64 ? grouped_steps<double>(b, nsteps, 0) : grouped_steps<float>(b, nsteps, 0);
     }
     if (rc) return rc;
     // after an odd number of steps B lives in the workspace: hand it back
@@ -353,13 +376,17 @@ int mx_batch_get_plan(mx_batch *b, int *sweeps_per_pass, int *tiles_total, int *
     if (!b) return bfail(MX_EINVAL, "batch is NULL");
     if (sweeps_per_pass) *sweeps_per_pass = b->spp;
     if (tiles_total) {
-        int rc = b->dtype == MX_F64 ? upload<double>(b, true) : upload<float>(b, true);
+        int rc = b->dtype == MX_F64 ? upload<double>(b, true, b->spp, b->Lf, b->Ls)
+                                    : upload<float>(b, true, b->spp, b->Lf, b->Ls);
         if (rc) return rc;
         *tiles_total = b->nf + b->ns;
     }
-    if (persistent_blocks)
-        *persistent_blocks = b->dtype == MX_F64 ? batch2d::persistent_blocks<double>(b->pq)
-                                                : batch2d::persistent_blocks<float>(b->pq);
+    if (persistent_blocks) {
+        int q, npass, nlow;
+        persistent_shape(b->m, b->pk, &q, &npass, &nlow);
+        *persistent_blocks = b->dtype == MX_F64 ? batch2d::persistent_blocks<double>(q)
+                                                : batch2d::persistent_blocks<float>(q);
+    }
     return MX_OK;
 }
 

@@ -112,13 +112,18 @@ hipError_t launch_front(const GridDesc<T> *d, int ng, const int *items, int nite
 template <typename T>
 hipError_t launch_sweep(const GridDesc<T> *d, int ng, const int *items, int nitems, int L, int k, bool first,
                         bool last, int xin, int xout, hipStream_t s);
-// co-resident workgroups of the persistent kernel for pass size q (0: unsupported q)
+constexpr int KMAX = 7;          // deepest batched pass (grouped or persistent)
+// co-resident workgroups of the persistent kernel whose deepest pass has q
+// sweeps (0: unsupported q)
 template <typename T>
 int persistent_blocks(int q);
+// all nsteps steps in one cooperative launch: per step the front, then npass
+// passes, the first nlow of q - 1 sweeps and the rest of q.  bar[0..2] and
+// *err must be zero at launch.
 template <typename T>
 hipError_t launch_persistent(const GridDesc<T> *d, int ng, const int *items_f, const int *items_s, int Lf, int Ls,
-                             int nsteps, int q, int npass, int bin0, unsigned *bar, int *err, int nblocks,
-                             hipStream_t s);
+                             int nsteps, int q, int npass, int nlow, int bin0, unsigned *bar, int *err,
+                             int nblocks, hipStream_t s);
 }  // namespace batch2d
 
 // 2D launchers (k2d.hip)

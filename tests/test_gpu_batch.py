@@ -72,6 +72,30 @@ def test_batch_schedules_agree_bitwise_fp32():
                 assert np.array_equal(a, s), (name, g)
 
 
+@pytest.mark.parametrize("m,spp", [(9, 5), (8, 5), (13, 7)])
+def test_batch_uneven_pass_depths_fp32(m, spp):
+    """Passes of different depths in one step (m = 9 with at most 5 per pass
+    runs 4 + 5; m = 8 runs 4 + 4 with 5 allowed; m = 13 runs 6 + 7), some of
+    them with aligned narrower strips: every column is still swept, and
+    both schedules equal the single-grid path bitwise."""
+    import torch
+    ws = _small_set("f32", seed=4400 + m)
+    for w in ws:
+        w.sweeps = m
+    res = {}
+    for pers in (False, True):
+        b, fields = _batch(ws, "f32", spp)
+        b.step(5, persistent=pers)
+        torch.cuda.synchronize()
+        res[pers] = [to_np(E + B) for E, B in fields]
+        b.close()
+    for g, w in enumerate(ws):
+        Eg, Bg, _, _ = run_gpu(w, 5, tol=0.0, sweeps=m)
+        for name, out in res.items():
+            for a, s_ in zip(out[g], Eg + Bg):
+                assert np.array_equal(a, s_), (m, spp, name, g)
+
+
 def test_batch_step_split_equals_one_call():
     """3 + 4 steps (odd count: B returns from the workspace) equal 7 steps."""
     import torch
