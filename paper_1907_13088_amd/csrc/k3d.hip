@@ -6,6 +6,8 @@
 // One thread per cell, 64 x 4 threads per workgroup along x and y, one z
 // plane per workgroup row of the grid; neighbour values come through the
 // vector caches.
+#include <algorithm>
+
 #include "mx_internal.h"
 
 namespace mx {
@@ -131,16 +133,16 @@ __global__ __launch_bounds__(NT) void k3_rhs(Coef<T> c, const T *Bx, const T *By
     }
 }
 
-// (A x)_component at the cell, 33-point stencil per component
-template <typename T>
-__device__ __forceinline__ void apply_A3(const Coef<T> &c, const Idx3 &id, const T *X, const T *Y,
-                                         const T *Z, T &ax, T &ay, T &az)
+// (A x)_component at a cell, 33-point stencil per component (eqs
+// matrixA_1st..matrixA_last).  X, Y, Z(di, dj, dk) return the iterate's
+// components at the cell offset by (di, dj, dk).
+template <typename T, typename FX, typename FY, typename FZ>
+__device__ __forceinline__ void apply_A3(const Coef<T> &c, FX &&X, FY &&Y, FZ &&Z, T &ax, T &ay, T &az)
 {
     const int L = 0;
-    auto d2 = [&](const T *F, int di, int dj, int dk, int ei, int ej, int ek) {
-        // second difference of F along axis e at offset d
-        return F[id.at(di + ei, dj + ej, dk + ek)] + F[id.at(di - ei, dj - ej, dk - ek)]
-               - T(2) * F[id.at(di, dj, dk)];
+    // second difference of F along axis e at offset d
+    auto d2 = [&](auto &&F, int di, int dj, int dk, int ei, int ej, int ek) {
+        return F(di + ei, dj + ej, dk + ek) + F(di - ei, dj - ej, dk - ek) - T(2) * F(di, dj, dk);
     };
     // --- x component: A_xx X + A_xy Y + A_xz Z
     {
@@ -148,12 +150,8 @@ __device__ __forceinline__ void apply_A3(const Coef<T> &c, const Idx3 &id, const
         const T dzz = d2(X, 0, 0, 0, 0, 0, 1);
         const T dyyzz = d2(X, 0, 1, 0, 0, 0, 1) + d2(X, 0, -1, 0, 0, 0, 1) - T(2) * dzz;
         // Dbar_x Dbar_y Y at (i+1/2, j, k+dk): Y at (i, j+1/2, k)
-        auto dxdyY = [&](int dk) {
-            return (Y[id.at(1, 0, dk)] - Y[id.at(1, -1, dk)]) - (Y[id.at(0, 0, dk)] - Y[id.at(0, -1, dk)]);
-        };
-        auto dxdzZ = [&](int dj) {
-            return (Z[id.at(1, dj, 0)] - Z[id.at(1, dj, -1)]) - (Z[id.at(0, dj, 0)] - Z[id.at(0, dj, -1)]);
-        };
+        auto dxdyY = [&](int dk) { return (Y(1, 0, dk) - Y(1, -1, dk)) - (Y(0, 0, dk) - Y(0, -1, dk)); };
+        auto dxdzZ = [&](int dj) { return (Z(1, dj, 0) - Z(1, dj, -1)) - (Z(0, dj, 0) - Z(0, dj, -1)); };
         ax = c.a3[0][0] * dyy + c.a3[0][1] * dzz + c.a3[0][2] * dyyzz
            + c.o3[2] * avg(dxdyY(-1), dxdyY(0), dxdyY(1), L)
            + c.o3[1] * avg(dxdzZ(-1), dxdzZ(0), dxdzZ(1), L);
@@ -163,12 +161,8 @@ __device__ __forceinline__ void apply_A3(const Coef<T> &c, const Idx3 &id, const
         const T dzz = d2(Y, 0, 0, 0, 0, 0, 1);
         const T dxx = d2(Y, 0, 0, 0, 1, 0, 0);
         const T dzzxx = d2(Y, 1, 0, 0, 0, 0, 1) + d2(Y, -1, 0, 0, 0, 0, 1) - T(2) * dzz;
-        auto dydxX = [&](int dk) {
-            return (X[id.at(0, 1, dk)] - X[id.at(-1, 1, dk)]) - (X[id.at(0, 0, dk)] - X[id.at(-1, 0, dk)]);
-        };
-        auto dydzZ = [&](int di) {
-            return (Z[id.at(di, 1, 0)] - Z[id.at(di, 1, -1)]) - (Z[id.at(di, 0, 0)] - Z[id.at(di, 0, -1)]);
-        };
+        auto dydxX = [&](int dk) { return (X(0, 1, dk) - X(-1, 1, dk)) - (X(0, 0, dk) - X(-1, 0, dk)); };
+        auto dydzZ = [&](int di) { return (Z(di, 1, 0) - Z(di, 1, -1)) - (Z(di, 0, 0) - Z(di, 0, -1)); };
         ay = c.a3[1][0] * dzz + c.a3[1][1] * dxx + c.a3[1][2] * dzzxx
            + c.o3[2] * avg(dydxX(-1), dydxX(0), dydxX(1), L)
            + c.o3[0] * avg(dydzZ(-1), dydzZ(0), dydzZ(1), L);
@@ -178,61 +172,125 @@ __device__ __forceinline__ void apply_A3(const Coef<T> &c, const Idx3 &id, const
         const T dxx = d2(Z, 0, 0, 0, 1, 0, 0);
         const T dyy = d2(Z, 0, 0, 0, 0, 1, 0);
         const T dxxyy = d2(Z, 0, 1, 0, 1, 0, 0) + d2(Z, 0, -1, 0, 1, 0, 0) - T(2) * dxx;
-        auto dzdxX = [&](int dj) {
-            return (X[id.at(0, dj, 1)] - X[id.at(-1, dj, 1)]) - (X[id.at(0, dj, 0)] - X[id.at(-1, dj, 0)]);
-        };
-        auto dzdyY = [&](int di) {
-            return (Y[id.at(di, 0, 1)] - Y[id.at(di, -1, 1)]) - (Y[id.at(di, 0, 0)] - Y[id.at(di, -1, 0)]);
-        };
+        auto dzdxX = [&](int dj) { return (X(0, dj, 1) - X(-1, dj, 1)) - (X(0, dj, 0) - X(-1, dj, 0)); };
+        auto dzdyY = [&](int di) { return (Y(di, 0, 1) - Y(di, -1, 1)) - (Y(di, 0, 0) - Y(di, -1, 0)); };
         az = c.a3[2][0] * dxx + c.a3[2][1] * dyy + c.a3[2][2] * dxxyy
            + c.o3[1] * avg(dzdxX(-1), dzdxX(0), dzdxX(1), L)
            + c.o3[0] * avg(dzdyY(-1), dzdyY(0), dzdyY(1), L);
     }
 }
 
+// One sweep pass, marching in z.  A workgroup of ZX x ZY threads owns a
+// ZX x ZY column tile and walks down a chunk of z planes; the iterate's
+// planes k-1, k, k+1 of the tile plus a one-cell halo in x and y sit in LDS
+// (three rotating plane slots), so each cell of the iterate is read from
+// HBM once per pass plus the halo.  Plane k+2 is prefetched into registers
+// while plane k is computed.
+constexpr int ZX = 64, ZY = 8, ZT = ZX * ZY;
+constexpr int PX = ZX + 2, PY = ZY + 2, PCELLS = PX * PY;
+constexpr int PLOAD = (PCELLS + ZT - 1) / ZT;   // halo-tile cells per thread
+
 template <typename T, bool DELTA>
-__global__ __launch_bounds__(NT) void k3_sweep(Coef<T> c, SweepArgs<T> a, int flags)
+__global__ __launch_bounds__(ZT) void k3_sweep(Coef<T> c, SweepArgs<T> a, int flags, int Lz)
 {
-    __shared__ double sred[2 * NT / 64];
-    Idx3 id{c.nx, c.ny, c.nz, 0, 0, 0};
-    const bool ok = cell(c.nx, c.ny, id);
+    __shared__ T pl[3][3][PY][PX];   // [slot][component][y][x]
+    __shared__ double sred[2 * ZT / 64];
+    const int nx = c.nx, ny = c.ny, nz = c.nz;
+    const int tid = threadIdx.x, tx = tid % ZX, ty = tid / ZX;
+    const int X0 = blockIdx.x * ZX, Y0 = blockIdx.y * ZY;
+    const int Z0 = blockIdx.z * Lz, Z1 = min(nz, Z0 + Lz);
+    const int gx = X0 + tx, gy = Y0 + ty;
+    const bool out = gx < nx && gy < ny;
+    const bool first = flags & SW_FIRST;
+    const T *xin[3], *cin[3];
+    for (int q = 0; q < 3; q++) {
+        xin[q] = first ? a.rhs[q] : a.x_in[q];
+        cin[q] = (DELTA && !first) ? a.s_in[q] : a.rhs[q];   // carried: dE' (standard), running sum (delta)
+    }
+    const size_t plane = (size_t)nx * ny;
+    // halo-tile cell offsets within a plane, fixed for the whole walk
+    size_t hoff[PLOAD];
+    int hidx[PLOAD];
+    for (int u = 0; u < PLOAD; u++) {
+        const int idx = tid + u * ZT;
+        hidx[u] = idx < PCELLS ? idx : -1;
+        const int ix = idx % PX, iy = idx / PX;
+        const int hx = wrap1(X0 - 1 + ix, nx), hy = wrap1(Y0 - 1 + iy, ny);
+        hoff[u] = (size_t)hy * nx + hx;
+    }
+    T pre[PLOAD][3];
+    auto fetch = [&](int k) {
+        const size_t zo = (size_t)wrap1(k, nz) * plane;
+        for (int u = 0; u < PLOAD; u++)
+            if (hidx[u] >= 0)
+                for (int q = 0; q < 3; q++) pre[u][q] = xin[q][zo + hoff[u]];
+    };
+    auto deposit = [&](int slot) {
+        for (int u = 0; u < PLOAD; u++)
+            if (hidx[u] >= 0)
+                for (int q = 0; q < 3; q++) (&pl[slot][q][0][0])[hidx[u]] = pre[u][q];
+    };
+    const size_t own = (size_t)(out ? gy : 0) * nx + (out ? gx : 0);
+    T cnext[3] = {T(0), T(0), T(0)};
+    auto fetch_own = [&](int k) {
+        if (!out || k >= Z1) return;
+        for (int q = 0; q < 3; q++) cnext[q] = cin[q][(size_t)k * plane + own];
+    };
+
+    int sm = 0, s0 = 1, sp = 2;   // slots of planes k-1, k, k+1
+    fetch(Z0 - 1);
+    deposit(sm);
+    fetch(Z0);
+    deposit(s0);
+    fetch(Z0 + 1);
+    fetch_own(Z0);
     double acc = 0.0, dummy = 0.0;
-    if (ok) {
-        const bool first = flags & SW_FIRST;
-        const T *X = first ? a.rhs[0] : a.x_in[0];
-        const T *Y = first ? a.rhs[1] : a.x_in[1];
-        const T *Z = first ? a.rhs[2] : a.x_in[2];
-        T ax, ay, az;
-        apply_A3(c, id, X, Y, Z, ax, ay, az);
-        const size_t o = id.at(0, 0, 0);
-        T v[3];
-        if (!DELTA) {
-            v[0] = a.rhs[0][o] + ax; v[1] = a.rhs[1][o] + ay; v[2] = a.rhs[2][o] + az;
-        } else {
-            v[0] = ax; v[1] = ay; v[2] = az;
-        }
-        const T *xin[3] = {X, Y, Z};
-        for (int q = 0; q < 3; q++) {
-            if (flags & SW_RESID) {
-                const double d = DELTA ? (double)v[q] : (double)v[q] - (double)xin[q][o];
-                acc += d * d;
+    for (int k = Z0; k < Z1; k++) {
+        deposit(sp);
+        const T cown[3] = {cnext[0], cnext[1], cnext[2]};
+        __syncthreads();
+        if (k + 2 <= Z1) fetch(k + 2);
+        fetch_own(k + 1);
+        if (out) {
+            auto at = [&](int q) {
+                return [&, q](int di, int dj, int dk) {
+                    const int slot = dk < 0 ? sm : (dk > 0 ? sp : s0);
+                    return pl[slot][q][ty + 1 + dj][tx + 1 + di];
+                };
+            };
+            T ax, ay, az;
+            apply_A3(c, at(0), at(1), at(2), ax, ay, az);
+            const size_t o = (size_t)k * plane + own;
+            const T v[3] = {DELTA ? ax : cown[0] + ax, DELTA ? ay : cown[1] + ay, DELTA ? az : cown[2] + az};
+            for (int q = 0; q < 3; q++) {
+                if (flags & SW_RESID) {
+                    const double d = DELTA ? (double)v[q] : (double)v[q] - (double)pl[s0][q][ty + 1][tx + 1];
+                    acc += d * d;
+                }
+                const T sum = DELTA ? cown[q] + v[q] : T(0);
+                if (flags & SW_STORE) {
+                    a.x_out[q][o] = v[q];
+                    if (DELTA) a.s_out[q][o] = sum;
+                }
+                if (flags & SW_LAST) a.E[q][o] += DELTA ? sum : v[q];
             }
-            T sum = T(0);
-            if (DELTA) sum = (first ? a.rhs[q][o] : a.s_in[q][o]) + v[q];
-            if (flags & SW_STORE) {
-                a.x_out[q][o] = v[q];
-                if (DELTA) a.s_out[q][o] = sum;
-            }
-            if (flags & SW_LAST) a.E[q][o] += DELTA ? sum : v[q];
         }
+        __syncthreads();   // plane k-1 is read by everyone before its slot is refilled
+        const int t = sm; sm = s0; s0 = sp; sp = t;
     }
     if (flags & SW_RESID) {
-        block_sum2(acc, dummy, sred);
-        if (threadIdx.x == 0) {
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        const int lane = tid & 63, w = tid >> 6;
+        if (lane == 0) sred[w] = acc;
+        __syncthreads();
+        if (tid == 0) {
+            double s_ = 0.0;
+            for (int q = 0; q < ZT / 64; q++) s_ += sred[q];
             const size_t wg = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-            a.partial[2 * wg] = acc;
+            a.partial[2 * wg] = s_;
             a.partial[2 * wg + 1] = 0.0;
         }
+        (void)dummy;
     }
 }
 
@@ -284,10 +342,15 @@ template <typename T>
 hipError_t launch_sweep3d(const Coef<T> &c, bool delta, int flags, const SweepArgs<T> &a,
                           hipStream_t s, int *nwg)
 {
-    dim3 g = grid3(c.nx, c.ny, c.nz);
+    // z chunks: enough workgroups for two per CU, each chunk at least 16 planes
+    const int gx = (c.nx + ZX - 1) / ZX, gy = (c.ny + ZY - 1) / ZY;
+    int nzc = std::max(1, std::min(c.nz / 16, (512 + gx * gy - 1) / (gx * gy)));
+    const int Lz = (c.nz + nzc - 1) / nzc;
+    nzc = (c.nz + Lz - 1) / Lz;
+    dim3 g(gx, gy, nzc);
     *nwg = g.x * g.y * g.z;
-    if (delta) hipLaunchKernelGGL((k3_sweep<T, true>), g, dim3(NT), 0, s, c, a, flags);
-    else hipLaunchKernelGGL((k3_sweep<T, false>), g, dim3(NT), 0, s, c, a, flags);
+    if (delta) hipLaunchKernelGGL((k3_sweep<T, true>), g, dim3(ZT), 0, s, c, a, flags, Lz);
+    else hipLaunchKernelGGL((k3_sweep<T, false>), g, dim3(ZT), 0, s, c, a, flags, Lz);
     return hipGetLastError();
 }
 
