@@ -12,6 +12,8 @@ None so that no stale traffic is reported.
     python -m paper_1907_13088_amd.profsum --trace T.db --fetch F.db --write W.db \\
         --copy-bytes N --bench-json bench.json --kernel REGEX --out profiles/NAME.md \\
         --cmd-trace "..." --cmd-fetch "..." --cmd-write "..."
+    python -m paper_1907_13088_amd.profsum --trace T.db --title TITLE --cmd-trace "..." \\
+        [--bench-json bench.json] --out profiles/NAME.md
 """
 from __future__ import annotations
 
@@ -140,19 +142,36 @@ def summarize(trace, fetch, write, copy_bytes, bench_json, kernel_re, out, cmds)
     return out
 
 
+def trace_summary(trace, title, cmd, out, bench_json=None):
+    """Kernel statistics of one rocprofv3 --kernel-trace --stats run."""
+    L = [f"# rocprofv3 summary: {title} (MI355X, 1 GPU)", "", "kernel trace command: `" + cmd + "`", "",
+         "| kernel | calls | avg us | total ms | % |", "|---|---:|---:|---:|---:|"]
+    for n, c, tot, avg, pct in _stats(trace):
+        L.append(f"| {_short(n)} | {c} | {avg:.1f} | {tot / 1e3:.2f} | {pct:.1f} |")
+    if bench_json:
+        L += ["", "bench.py output of the same command:", "", "```",
+              open(bench_json).read().strip().splitlines()[-1], "```"]
+    open(out, "w").write("\n".join(L) + "\n")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
-    ap.add_argument("--copy-bytes", type=int, required=True)
+    ap.add_argument("--title", default=None, help="trace-only summary with this title")
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--copy-bytes", type=int)
     ap.add_argument("--bench-json", default=None)
-    ap.add_argument("--kernel", required=True, help="regex of the dominant kernel's name")
+    ap.add_argument("--kernel", help="regex of the dominant kernel's name")
     ap.add_argument("--out", required=True)
     ap.add_argument("--cmd-trace", required=True)
-    ap.add_argument("--cmd-fetch", required=True)
-    ap.add_argument("--cmd-write", required=True)
+    ap.add_argument("--cmd-fetch")
+    ap.add_argument("--cmd-write")
     a = ap.parse_args()
+    if a.title:
+        print(trace_summary(a.trace, a.title, a.cmd_trace, a.out, a.bench_json))
+        return
     print(summarize(a.trace, a.fetch, a.write, a.copy_bytes, a.bench_json, a.kernel, a.out,
                     (a.cmd_trace, a.cmd_fetch, a.cmd_write)))
 
