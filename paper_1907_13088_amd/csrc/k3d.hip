@@ -215,7 +215,8 @@ __global__ __launch_bounds__(ZT) void k3_sweep(Coef<T> c, SweepArgs<T> a, int fl
         const int idx = tid + u * ZT;
         hidx[u] = idx < PCELLS ? idx : -1;
         const int ix = idx % PX, iy = idx / PX;
-        const int hx = wrap1(X0 - 1 + ix, nx), hy = wrap1(Y0 - 1 + iy, ny);
+        // full modulo: a tile may be wider than the grid
+        const int hx = ((X0 - 1 + ix) % nx + nx) % nx, hy = ((Y0 - 1 + iy) % ny + ny) % ny;
         hoff[u] = (size_t)hy * nx + hx;
     }
     T pre[PLOAD][3];

@@ -215,3 +215,62 @@ def test_tiny_grids(variant):
         Eg, Bg, _, _ = run_gpu(w, 3, spp=4, variant=variant)
         Eo, Bo, _ = run_oracle(w, 3)
         assert max(rel_err(Eg + Bg, Eo + Bo)) < 1e-12, n
+
+
+def test_full_size_fp32_single_modes_after_1000_steps():
+    """4096^2 FP32, m = 20, 1000 steps (the full 2D workload's grid, step
+    count and solve): one TE and one TM discrete eigenmode of the step matrix
+    T(k) evolve as lambda^n v; the state error and the frequency error stay
+    within 1e-5 relative."""
+    import torch
+    from oracle import spectral as S
+    n, m, nsteps = 4096, 20, 1000
+    dt = I.round_to(np.float32, I.courant_dt(0.5, (1, 1)))
+    modes = []
+    for nidx, te in (((37, 11), True), ((5, -23), False)):
+        k = [2 * math.pi * nidx[0] / n, 2 * math.pi * nidx[1] / n]
+        T = S.step_matrix(k, (1, 1), dt, m)
+        lam, vec = np.linalg.eig(T)
+        comps = (0, 1, 5) if te else (2, 3, 4)
+        best = None
+        for j in range(6):
+            v = vec[:, j]
+            if np.angle(lam[j]) < -1e-9 and np.linalg.norm(v[list(comps)]) > 0.99 * np.linalg.norm(v):
+                best = (lam[j], v / np.abs(v).max())
+        assert best is not None
+        modes.append((k, best[0], best[1]))
+    offs = list(I.E_OFFSETS[2]) + list(I.B_OFFSETS[2])
+    shape = (n, n)
+    x = np.arange(n, dtype=np.float64)
+    fields = []
+    for c in range(6):
+        f = np.zeros(shape)
+        for k, lam, v in modes:
+            ph = (k[0] * (x + offs[c][0]))[None, :] + (k[1] * (x + offs[c][1]))[:, None]
+            f += np.real(v[c] * np.exp(1j * ph))
+        fields.append(I.round_to(np.float32, f))
+    cfg = mx.make_config(2, (n, n), dt, (1.0, 1.0), "f32", mx.MX_ALL, m, 0.0, 0)
+    g = mx.Grid(cfg)
+    E = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in fields[:3]]
+    B = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in fields[3:]]
+    g.bind(E, B)
+    g.step(nsteps)
+    torch.cuda.synchronize()
+    xs = torch.arange(n, dtype=torch.float64, device="cuda")
+
+    def proj(t, k, off):
+        ph = (k[0] * (xs + off[0]))[None, :] + (k[1] * (xs + off[1]))[:, None]
+        return complex((t.double() * torch.exp(-1j * ph)).sum().item()) * 2 / (n * n)
+
+    for k, lam, v in modes:
+        got = np.array([proj(t, k, offs[c]) for c, t in enumerate(E + B)])
+        want = lam ** nsteps * v
+        err = np.abs(got - want).max() / np.abs(want).max()
+        c = int(np.argmax(np.abs(want)))
+        dphi = np.angle(got[c] / want[c])
+        w = abs(np.angle(lam)) / dt
+        werr = abs(dphi) / (nsteps * dt) / w
+        log(f"mode k={k}: state error {err:.2e}, omega error {werr:.2e} after {nsteps} steps")
+        assert err < 1e-5
+        assert werr < 1e-5
+
