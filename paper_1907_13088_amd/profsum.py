@@ -53,6 +53,7 @@ def traffic_per_launch(path: str):
 
 
 def _short(n: str) -> str:
+    n = n.replace("(anonymous namespace)::", "")
     n = re.sub(r"\(.*", "", n)
     return n.replace("void ", "").replace("mx::", "")
 
