@@ -295,6 +295,132 @@ __global__ __launch_bounds__(ZT) void k3_sweep(Coef<T> c, SweepArgs<T> a, int fl
     }
 }
 
+// Two sweeps per pass (FP32), marching in z.  A workgroup of YX x YY
+// threads owns a YX x YY column tile; each thread carries its own column
+// through both sweep levels: level 0 (the input iterate) is loaded by every
+// thread, level 1 is computed by the threads one cell inside the tile edge,
+// level 2 (the pass output) by those two cells inside, so the output tile is
+// (YX - 4) x (YY - 4).  Level 1 lags level 0 by one plane and level 2 lags
+// level 1 by one plane; each level keeps three plane slots in LDS.  The
+// carried value (dE' in the standard form, the running sum in the delta
+// form) of a thread's own cell passes from level 1 to level 2 in registers.
+constexpr int YX = 64, YY = 16, YT = YX * YY;
+constexpr int YOX = YX - 4, YOY = YY - 4;
+
+template <typename T, bool DELTA>
+__global__ __launch_bounds__(YT) void k3_sweep2(Coef<T> c, SweepArgs<T> a, int flags, int Lz)
+{
+    __shared__ T l0[3][3][YY][YX];   // [slot][component][y][x]
+    __shared__ T l1[3][3][YY][YX];
+    __shared__ double sred[YT / 64];
+    const int nx = c.nx, ny = c.ny, nz = c.nz;
+    const int tid = threadIdx.x, tx = tid % YX, ty = tid / YX;
+    const int X0 = blockIdx.x * YOX, Y0 = blockIdx.y * YOY;
+    const int Z0 = blockIdx.z * Lz, Z1 = min(nz, Z0 + Lz);
+    // own column (level 0 is loaded at every tile cell, wrapped)
+    const int ux = X0 - 2 + tx, uy = Y0 - 2 + ty;
+    const int gx = ((ux % nx) + nx) % nx, gy = ((uy % ny) + ny) % ny;
+    const bool in1 = tx >= 1 && tx < YX - 1 && ty >= 1 && ty < YY - 1;
+    const bool in2 = tx >= 2 && tx < YX - 2 && ty >= 2 && ty < YY - 2 && ux < nx && uy < ny;
+    const bool first = flags & SW_FIRST;
+    const T *xin[3], *cin[3];
+    for (int q = 0; q < 3; q++) {
+        xin[q] = first ? a.rhs[q] : a.x_in[q];
+        cin[q] = (DELTA && !first) ? a.s_in[q] : a.rhs[q];
+    }
+    const size_t plane = (size_t)nx * ny;
+    const size_t own = (size_t)gy * nx + gx;
+    auto zoff = [&](int k) { return (size_t)((k % nz + nz) % nz) * plane; };
+    auto slot = [](int k) { return ((k % 3) + 3) % 3; };
+
+    T pre[3];
+    auto fetch0 = [&](int k) {
+        const size_t o = zoff(k) + own;
+        for (int q = 0; q < 3; q++) pre[q] = xin[q][o];
+    };
+    // carried value of level 1 (plane k - 1) and of level 2 (plane k - 2)
+    T c1[3] = {T(0), T(0), T(0)}, c2[3] = {T(0), T(0), T(0)}, x1own[3] = {T(0), T(0), T(0)};
+    double acc = 0.0;
+    const int kb = Z0 - 2, ke = Z1 + 1;   // level-0 planes of the walk
+    fetch0(kb);
+    for (int k = kb; k <= ke; k++) {
+        {
+            const int s0 = slot(k);
+            for (int q = 0; q < 3; q++) l0[s0][q][ty][tx] = pre[q];
+        }
+        if (k + 1 <= ke) fetch0(k + 1);
+        // the carried input of level 1 for plane k - 1 (own cell)
+        T cin1[3] = {T(0), T(0), T(0)};
+        const int k1 = k - 1, k2 = k - 2;
+        const bool act1 = k1 >= Z0 - 1 && k1 <= Z1 && in1;
+        if (act1) {
+            const size_t o = zoff(k1) + own;
+            for (int q = 0; q < 3; q++) cin1[q] = cin[q][o];
+        }
+        __syncthreads();
+        // level 1, plane k - 1
+        T n1[3] = {T(0), T(0), T(0)}, s1[3] = {T(0), T(0), T(0)};
+        if (act1) {
+            const int sm = slot(k1 - 1), s0 = slot(k1), sp = slot(k1 + 1);
+            auto at = [&](int q) {
+                return [&, q](int di, int dj, int dk) {
+                    return l0[dk < 0 ? sm : (dk > 0 ? sp : s0)][q][ty + dj][tx + di];
+                };
+            };
+            T ax, ay, az;
+            apply_A3(c, at(0), at(1), at(2), ax, ay, az);
+            const T av[3] = {ax, ay, az};
+            for (int q = 0; q < 3; q++) {
+                n1[q] = DELTA ? av[q] : cin1[q] + av[q];
+                s1[q] = DELTA ? cin1[q] + n1[q] : cin1[q];
+                l1[s0][q][ty][tx] = n1[q];
+            }
+        }
+        __syncthreads();
+        // level 2, plane k - 2 (inputs: level-1 planes k - 3 .. k - 1)
+        if (k2 >= Z0 && k2 < Z1 && in2) {
+            const int sm = slot(k2 - 1), s0 = slot(k2), sp = slot(k2 + 1);
+            auto at = [&](int q) {
+                return [&, q](int di, int dj, int dk) {
+                    return l1[dk < 0 ? sm : (dk > 0 ? sp : s0)][q][ty + dj][tx + di];
+                };
+            };
+            T ax, ay, az;
+            apply_A3(c, at(0), at(1), at(2), ax, ay, az);
+            const T av[3] = {ax, ay, az};
+            const size_t o = (size_t)k2 * plane + (size_t)uy * nx + ux;
+            for (int q = 0; q < 3; q++) {
+                const T v = DELTA ? av[q] : c2[q] + av[q];
+                const T sum = DELTA ? c2[q] + v : T(0);
+                if (flags & SW_RESID) {
+                    const double d = DELTA ? (double)v : (double)v - (double)x1own[q];
+                    acc += d * d;
+                }
+                if (flags & SW_STORE) {
+                    a.x_out[q][o] = v;
+                    if (DELTA) a.s_out[q][o] = sum;
+                }
+                if (flags & SW_LAST) a.E[q][o] += DELTA ? sum : v;
+            }
+        }
+        // level 1's own results of plane k - 1 become level 2's inputs next step
+        for (int q = 0; q < 3; q++) { c2[q] = s1[q]; x1own[q] = n1[q]; }
+    }
+    if (flags & SW_RESID) {
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        const int lane = tid & 63, w = tid >> 6;
+        if (lane == 0) sred[w] = acc;
+        __syncthreads();
+        if (tid == 0) {
+            double s_ = 0.0;
+            for (int q = 0; q < YT / 64; q++) s_ += sred[q];
+            const size_t wg = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+            a.partial[2 * wg] = s_;
+            a.partial[2 * wg + 1] = 0.0;
+        }
+    }
+}
+
 dim3 grid3(int nx, int ny, int nz) { return dim3((nx + BXT - 1) / BXT, (ny + BYT - 1) / BYT, nz); }
 
 }  // namespace
@@ -340,9 +466,24 @@ hipError_t launch_rhs3d(const Coef<T> &c, const T *const B[3], const T *const Jf
 }
 
 template <typename T>
-hipError_t launch_sweep3d(const Coef<T> &c, bool delta, int flags, const SweepArgs<T> &a,
+hipError_t launch_sweep3d(const Coef<T> &c, int k, bool delta, int flags, const SweepArgs<T> &a,
                           hipStream_t s, int *nwg)
 {
+    if constexpr (sizeof(T) == 4) {
+        if (k == 2) {
+        // enough workgroups for whole rounds of one per CU, chunks of >= 16 planes
+        const int gx = (c.nx + YOX - 1) / YOX, gy = (c.ny + YOY - 1) / YOY;
+        int nzc = std::max(1, std::min(c.nz / 16, (2 * 256 + gx * gy - 1) / (gx * gy)));
+        const int Lz = (c.nz + nzc - 1) / nzc;
+        nzc = (c.nz + Lz - 1) / Lz;
+        dim3 g(gx, gy, nzc);
+        *nwg = g.x * g.y * g.z;
+        if (delta) hipLaunchKernelGGL((k3_sweep2<T, true>), g, dim3(YT), 0, s, c, a, flags, Lz);
+        else hipLaunchKernelGGL((k3_sweep2<T, false>), g, dim3(YT), 0, s, c, a, flags, Lz);
+        return hipGetLastError();
+        }
+    }
+    if (k != 1) return hipErrorInvalidValue;
     // z chunks: enough workgroups for two per CU, each chunk at least 16 planes
     const int gx = (c.nx + ZX - 1) / ZX, gy = (c.ny + ZY - 1) / ZY;
     int nzc = std::max(1, std::min(c.nz / 16, (512 + gx * gy - 1) / (gx * gy)));
@@ -361,7 +502,7 @@ hipError_t launch_sweep3d(const Coef<T> &c, bool delta, int flags, const SweepAr
     template hipError_t launch_faraday3d<T>(const Coef<T> &, const T *const[3], T *const[3], hipStream_t); \
     template hipError_t launch_rhs3d<T>(const Coef<T> &, const T *const[3], const T *const[3], T,     \
                                         T *const[3], double *, hipStream_t, int *);                   \
-    template hipError_t launch_sweep3d<T>(const Coef<T> &, bool, int, const SweepArgs<T> &, hipStream_t, int *);
+    template hipError_t launch_sweep3d<T>(const Coef<T> &, int, bool, int, const SweepArgs<T> &, hipStream_t, int *);
 INST(float)
 INST(double)
 #undef INST

@@ -61,7 +61,14 @@ int64_t max_wg(const mx_config *c)
 // stopping test.
 void pass_depths(const mx_config *c, int variant, int out[2])
 {
-    if (c->ndim == 3) { out[0] = out[1] = 1; return; }
+    if (c->ndim == 3) {
+        // 3D: one sweep per pass by default; FP32 may ask for two (the
+        // two-level z-marching kernel, measured slower on 512^3: its tile
+        // spends a third of its lanes on halo cells)
+        const int kmax = c->dtype == MX_F64 ? 1 : 2;
+        out[0] = out[1] = c->sweeps_per_pass > 0 ? std::min(c->sweeps_per_pass, kmax) : 1;
+        return;
+    }
     const bool f64 = c->dtype == MX_F64;
     if (variant == 1) {
         const int k = c->sweeps_per_pass > 0 ? c->sweeps_per_pass : (f64 ? 4 : 5);
@@ -234,7 +241,8 @@ int mx_validate(const mx_config *c, int *warn)
     if (c->variant < 0 || c->variant > 3) return fail(MX_EINVAL, "variant must be 0, 1, 2 or 3");
     if (c->variant == 1 && c->sweeps_per_pass > 8)
         return fail(MX_EINVAL, "the LDS-tile kernel runs at most 8 sweeps per pass");
-    if (c->ndim == 3 && c->sweeps_per_pass > 1) return fail(MX_EINVAL, "3D grids run one sweep per pass");
+    if (c->ndim == 3 && c->sweeps_per_pass > (c->dtype == MX_F64 ? 1 : 2))
+        return fail(MX_EINVAL, "3D grids run at most two sweeps per pass in FP32, one in FP64");
     if (!(c->dt > 0.0) || !std::isfinite(c->dt)) return fail(MX_EINVAL, "dt must be positive and finite");
     double s = 0.0;
     for (int a = 0; a < c->ndim; a++) s += 1.0 / (c->d[a] * c->d[a]);
@@ -492,7 +500,7 @@ int run_sweeps(mx_grid *g, void *const rhs[3], const int *target_in, bool tolmod
                              (double)g->ncell * sizeof(T) * arrs * ncomp);
                 if (c.ndim == 2 && g->variant == 1) e = launch_sweep2d<T>(k, act, kk, delta, flags, a, g->stream, &nwg);
                 else if (c.ndim == 2) e = launch_stream2d<T>(k, act, kk, delta, flags, a, g->stream, &nwg, 0);
-                else e = launch_sweep3d<T>(k, delta, flags, a, g->stream, &nwg);
+                else e = launch_sweep3d<T>(k, kk, delta, flags, a, g->stream, &nwg);
             }
             if (e != hipSuccess) return fail(MX_EDEVICE, "sweep launch: %s", hipGetErrorString(e));
             for (int b = 0; b < nblk; b++)

@@ -55,6 +55,8 @@ def _cfg(**kw):
     (dict(sweeps_per_pass=9, variant=1), mx.MX_EINVAL),
     (dict(form=7), mx.MX_EINVAL),
     (dict(ndim=3, n=(8, 8, 8), dt=0.5 / math.sqrt(3), blocks=1), mx.MX_EINVAL),
+    (dict(ndim=3, n=(8, 8, 8), dt=0.5 / math.sqrt(3), sweeps_per_pass=3), mx.MX_EINVAL),
+    (dict(ndim=3, n=(8, 8, 8), dt=0.5 / math.sqrt(3), dtype="f64", sweeps_per_pass=2), mx.MX_EINVAL),
     (dict(ndim=3, n=(8, 8, 8), dt=0.99 / math.sqrt(2)), mx.MX_ECFL),
 ])
 def test_validation_errors(kw, code):

@@ -71,6 +71,26 @@ def test_3d_fp32_delta_tolerance_1e7():
     assert max(e) < 1e-5
 
 
+@pytest.mark.parametrize("shape", [(20, 22, 23), (17, 40, 70), (5, 3, 7)])
+def test_3d_fp32_two_level_pass_equals_single_level_bitwise(shape):
+    """FP32 passes of two sweeps (z-marching, two LDS levels) against passes
+    of one sweep: the same stencil arithmetic in the same order, so the
+    fields agree bitwise; both within 1e-5 of the oracle.  Ragged shapes,
+    some smaller than a workgroup tile."""
+    w = I.planewave_3d(n=72, kidx=2, npulses=4, sigma=3.0, filter_passes=1, tol=0.0, m_max=9, steps=6,
+                       seed=3010, dtype="f32")
+    w = _reshape(w, shape)
+    E2, B2, _, k2 = run_gpu(w, 4, sweeps=9, tol=0.0, spp=2)
+    E1, B1, _, k1 = run_gpu(w, 4, sweeps=9, tol=0.0)
+    assert (k2, k1) == (2, 1)
+    for a, b in zip(E2 + B2, E1 + B1):
+        assert np.array_equal(a, b)
+    Eo, Bo, _ = run_oracle(w, 4, sweeps=9, tol=0.0)
+    e = rel_err(E2 + B2, Eo + Bo)
+    log(f"3D fp32 two-level {shape}: {max(e):.2e}")
+    assert max(e) < 1e-5
+
+
 def test_3d_lumped_yee(small3d):
     w = small3d
     Eg, Bg, st, _ = run_gpu(w, 4, lumped=True, tol=0.0, sweeps=5)
