@@ -55,15 +55,16 @@ KMAX_F64 = {mx.VARIANT_STREAM: (3, 3), mx.VARIANT_STREAM_BLOCK: (5, 8)}
 VARIANTS = [mx.VARIANT_TILE, mx.VARIANT_STREAM, mx.VARIANT_STREAM_BLOCK]
 
 
-@pytest.mark.parametrize("variant", VARIANTS)
-@pytest.mark.parametrize("spp", [1, 2, 3, 4, 5, 6, 7, 8, 16])
+# the LDS-tile kernel fuses at most 8 sweeps; the joint FP64 streaming pass
+# caps at 3, so 4 already exercises the cap
+DEPTHS = ([(mx.VARIANT_TILE, k) for k in range(1, 9)] + [(mx.VARIANT_STREAM, k) for k in range(1, 5)]
+          + [(mx.VARIANT_STREAM_BLOCK, k) for k in (1, 2, 3, 4, 5, 6, 7, 8, 16)])
+
+
+@pytest.mark.parametrize("variant,spp", DEPTHS)
 def test_modes_fp64_every_pass_depth(small_modes, spp, variant):
     w = small_modes
     nsteps = 12
-    if variant == mx.VARIANT_TILE and spp > 8:
-        pytest.skip("the LDS-tile kernel fuses at most 8 sweeps")
-    if variant == mx.VARIANT_STREAM and spp > 4:
-        pytest.skip("covered by the smaller depths (capped at 3)")
     cfg = gpu_config(w, spp=spp, variant=variant)
     g = mx.Grid(cfg)
     want = (spp, spp) if variant == mx.VARIANT_TILE else tuple(min(spp, k) for k in KMAX_F64[variant])
@@ -75,6 +76,21 @@ def test_modes_fp64_every_pass_depth(small_modes, spp, variant):
     e = rel_err(Eg + Bg, Eo + Bo)
     log(f"variant={variant} spp={spp} fp64 errors {max(e):.3e}")
     assert max(e) < 1e-12
+
+
+def test_wide_ragged_grid_every_strip_geometry():
+    """700 x 300 (several strips per row: 480-column aligned front strips,
+    224-column aligned strips of passes up to 4 sweeps, 256 - 2k columns
+    beyond), FP64 with current and filter: every pass depth class and both
+    streaming variants against the oracle."""
+    w = I.modes_2d((700, 300), nmodes=40, npulses=6, filter_passes=3, m=20, steps=4, seed=2011, dtype="f64")
+    Eo, Bo, _ = run_oracle(w, 4)
+    for variant, spp in ((mx.VARIANT_STREAM, 3), (mx.VARIANT_STREAM_BLOCK, 4), (mx.VARIANT_STREAM_BLOCK, 0),
+                         (mx.VARIANT_STREAM, 0)):
+        Eg, Bg, _, _ = run_gpu(w, 4, spp=spp, variant=variant)
+        e = rel_err(Eg + Bg, Eo + Bo)
+        log(f"700x300 variant={variant} spp={spp}: {max(e):.2e}")
+        assert max(e) < 1e-12, (variant, spp)
 
 
 def test_pass_depth_and_kernel_invariance_is_bitwise(small_modes):
