@@ -276,9 +276,7 @@ __global__ __launch_bounds__(RX) void k2_front_stream(Coef<T> c, FrontArgs<T> a,
                                                       const T *Bin1, const T *Bin2, int L, int nsx, int nwg)
 {
     const int b = blockIdx.x;
-    const int per = (nwg + 7) / 8;
-    int wid = (b % 8) * per + b / 8;   // consecutive chunks on one XCD
-    if (nwg % 8 != 0 || wid >= nwg) wid = b;
+    const int wid = xcd_map(blockIdx.x, nwg);
     __shared__ __attribute__((aligned(16))) char lds[front_lds_bytes<T, P, RX>()];
     __shared__ double sred[2 * RX / 64];
     front_tile<T, BLK, P, RX, HASJ>(c, a, Bin0, Bin1, Bin2, L, nsx, wid, b, lds, sred);

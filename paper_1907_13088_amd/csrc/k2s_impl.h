@@ -351,22 +351,12 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
     lds_barrier();   // the LDS rows are reused by the caller's next item
 }
 
-// work item of a single-grid launch: consecutive chunks of a strip go to the
-// same XCD (workgroups are dealt round-robin over the 8 XCDs)
-__device__ __forceinline__ int xcd_item(int nwg)
-{
-    const int b = blockIdx.x;
-    const int per = (nwg + 7) / 8;
-    const int wid = (b % 8) * per + b / 8;
-    return (nwg % 8 != 0 || wid >= nwg) ? b : wid;
-}
-
 template <typename T, int BLK, int K, bool DELTA, int RX, int OM>
 __global__ __launch_bounds__(RX) void k2_stream(Coef<T> c, SweepArgs<T> a, int flags, int L, int nsx, int nwg)
 {
     __shared__ __attribute__((aligned(16))) char lds[stream_lds_bytes<T, BLK, K, RX>()];
     __shared__ double sred[2 * RX / 64];
-    stream_tile<T, BLK, K, DELTA, RX, OM>(c, a, flags, L, nsx, xcd_item(nwg), blockIdx.x, lds, sred);
+    stream_tile<T, BLK, K, DELTA, RX, OM>(c, a, flags, L, nsx, xcd_map(blockIdx.x, nwg), blockIdx.x, lds, sred);
 }
 
 constexpr int SRX = 256;   // threads (columns) per workgroup strip

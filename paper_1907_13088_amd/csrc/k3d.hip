@@ -48,12 +48,25 @@ __device__ void block_sum2(double &a, double &b, double *sh)
     }
 }
 
+// Tile (x, y, z-chunk) of this workgroup: tiles are numbered x-fastest and
+// dealt to the XCDs in contiguous ranges, so that a tile and its x and y
+// neighbours mostly share one L2.
+__device__ __forceinline__ int3 tile_of_block()
+{
+    const int n = gridDim.x * gridDim.y * gridDim.z;
+    const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const int t = xcd_map(b, n);
+    const int gxy = gridDim.x * gridDim.y;
+    return make_int3(t % gridDim.x, (t % gxy) / gridDim.x, t / gxy);
+}
+
 __device__ __forceinline__ bool cell(int nx, int ny, Idx3 &id)
 {
     const int tx = threadIdx.x & (BXT - 1), ty = threadIdx.x / BXT;
-    id.i = blockIdx.x * BXT + tx;
-    id.j = blockIdx.y * BYT + ty;
-    id.k = blockIdx.z;
+    const int3 tile = tile_of_block();
+    id.i = tile.x * BXT + tx;
+    id.j = tile.y * BYT + ty;
+    id.k = tile.z;
     return id.i < nx && id.j < ny;
 }
 
@@ -197,8 +210,9 @@ __global__ __launch_bounds__(ZT) void k3_sweep(Coef<T> c, SweepArgs<T> a, int fl
     __shared__ double sred[2 * ZT / 64];
     const int nx = c.nx, ny = c.ny, nz = c.nz;
     const int tid = threadIdx.x, tx = tid % ZX, ty = tid / ZX;
-    const int X0 = blockIdx.x * ZX, Y0 = blockIdx.y * ZY;
-    const int Z0 = blockIdx.z * Lz, Z1 = min(nz, Z0 + Lz);
+    const int3 tile = tile_of_block();
+    const int X0 = tile.x * ZX, Y0 = tile.y * ZY;
+    const int Z0 = tile.z * Lz, Z1 = min(nz, Z0 + Lz);
     const int gx = X0 + tx, gy = Y0 + ty;
     const bool out = gx < nx && gy < ny;
     const bool first = flags & SW_FIRST;
@@ -315,8 +329,9 @@ __global__ __launch_bounds__(YT) void k3_sweep2(Coef<T> c, SweepArgs<T> a, int f
     __shared__ double sred[YT / 64];
     const int nx = c.nx, ny = c.ny, nz = c.nz;
     const int tid = threadIdx.x, tx = tid % YX, ty = tid / YX;
-    const int X0 = blockIdx.x * YOX, Y0 = blockIdx.y * YOY;
-    const int Z0 = blockIdx.z * Lz, Z1 = min(nz, Z0 + Lz);
+    const int3 tile = tile_of_block();
+    const int X0 = tile.x * YOX, Y0 = tile.y * YOY;
+    const int Z0 = tile.z * Lz, Z1 = min(nz, Z0 + Lz);
     // own column (level 0 is loaded at every tile cell, wrapped)
     const int ux = X0 - 2 + tx, uy = Y0 - 2 + ty;
     const int gx = ((ux % nx) + nx) % nx, gy = ((uy % ny) + ny) % ny;

@@ -77,7 +77,7 @@ __global__ __launch_bounds__(RX) void kb_front(const GridDesc<T> *d, int ng, con
 {
     __shared__ __attribute__((aligned(16))) char lds[front2d::front_lds_bytes<T, 0, RX>()];
     __shared__ double sred[2 * RX / 64];
-    front_item<T>(d, ng, items, L, bin, blockIdx.x, lds, sred);
+    front_item<T>(d, ng, items, L, bin, xcd_map(blockIdx.x, gridDim.x), lds, sred);
 }
 
 template <typename T, int K, int OM>
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(RX) void kb_sweep(const GridDesc<T> *d, int ng, con
 {
     __shared__ __attribute__((aligned(16))) char lds[stream2d::stream_lds_bytes<T, 3, K, RX>()];
     __shared__ double sred[2 * RX / 64];
-    sweep_item<T, K, OM>(d, ng, items, L, first != 0, xin, xout, blockIdx.x, lds, sred);
+    sweep_item<T, K, OM>(d, ng, items, L, first != 0, xin, xout, xcd_map(blockIdx.x, gridDim.x), lds, sred);
 }
 
 // Grid-wide barrier for a cooperative launch.  bar[0] counts arrivals,

@@ -66,6 +66,20 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Work item of workgroup b (linear index) in a launch of n workgroups, such
+// that each XCD receives one contiguous range of items.  Workgroups are dealt
+// round-robin over the 8 XCDs (workgroup b runs on XCD b % 8), so XCD x holds
+// q + (x < r) of them for n = 8 q + r; the map is a bijection of [0, n) for
+// any n.  The kernels number their tiles x-fastest, so tiles that neighbour
+// each other run on one XCD at the same time and share the L2 lines of their
+// halos.
+__device__ __forceinline__ int xcd_map(int b, int n)
+{
+    const int x = b & 7, j = b >> 3;
+    const int q = n >> 3, r = n & 7;
+    return x * q + (x < r ? x : r) + j;
+}
+
 // Element access by a 32-bit byte offset from a uniform base: lets the
 // compiler use the scalar-base + vector-offset addressing form, one offset
 // register shared by every component of a row.  Arrays are below 4 GiB.
