@@ -184,6 +184,15 @@ def main():
                 "valu_peak_tflops": VALU_FP32_PEAK_TFLOPS,
                 "step_hbm_GBps": round(sum(v["bytes"] for v in prof.values()) / (total_ms / 1e3) / 1e9, 1)}
 
+    # bytes per cell-step: this schedule's (the per-launch algorithmic bytes of
+    # every kernel category) against the unfused schedule (Faraday 9 words,
+    # each filter pass 6 words per axis, auxiliary increment 9, each sweep 9,
+    # E increment 9; FP32 words)
+    fused_b = sum(v["bytes"] for v in prof.values()) / (ncell * K)
+    unfused_b = 4.0 * (9 + 12 * w.filter_passes + 9 + 9 * w.sweeps + 9)
+    bytes_model = {"fused_B_per_cell_step": round(fused_b, 1), "unfused_B_per_cell_step": unfused_b,
+                   "unfused_equivalent_GBps": round(unfused_b * value, 1)}
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import ref
@@ -222,6 +231,7 @@ def main():
         "fp64": fp64,
         "roofline": roofline,
         "kernels": kernels,
+        "bytes_model": bytes_model,
         "cpu_baseline": cpu,
     }
     g32.close()
