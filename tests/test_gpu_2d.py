@@ -290,3 +290,51 @@ def test_full_size_fp32_single_modes_after_1000_steps():
         assert err < 1e-5
         assert werr < 1e-5
 
+
+
+def _window(w, cy, cx, size):
+    """The workload restricted to a size x size window centred at (cy, cx),
+    cut from the periodic arrays (every component keeps its staggering)."""
+    import dataclasses
+    ny, nx = w.shape
+    rows = (cy - size // 2 + np.arange(size)) % ny
+    cols = (cx - size // 2 + np.arange(size)) % nx
+    cut = lambda arrs: [np.ascontiguousarray(a[np.ix_(rows, cols)]) for a in arrs]
+    return dataclasses.replace(w, shape=(size, size), E=cut(w.E), B=cut(w.B),
+                               J0=None if w.J0 is None else cut(w.J0))
+
+
+def test_full_size_modes_sampled_windows_in_bench_configuration():
+    """4096^2 FP32 TE+TM with current, 3-pass filter and m = 20 (the full 2D
+    workload, in the launch configuration the benchmark times), 2 steps.
+    One step of an output cell depends on inputs within about 25 cells
+    (filter 3, curls 2, 20 sweeps of a 3 x 3 stencil), so the oracle run on a
+    periodic window with a 64-cell margin per side reproduces the window's
+    core exactly; checked here by running the oracle on two window sizes.
+    Sampled cores (4 windows of 32 x 32 cells) are compared with the GPU, in
+    FP32 (within 1e-5) and in FP64 (the FP64 leg of the benchmark, within
+    1e-12)."""
+    n, nsteps, core, margin = 4096, 2, 32, 64
+    w = I.modes_2d((n, n), steps=nsteps, dtype="f32")
+    log("full-size windows: gpu runs")
+    runs = [("f32", 1e-5, run_gpu(w, nsteps)), ("f64", 1e-12, run_gpu(w, nsteps, dtype="f64"))]
+    rng = np.random.default_rng(4096)
+    centres = [(0, 0), (n - 1, n // 2)] + [tuple(int(v) for v in rng.integers(0, n, 2)) for _ in range(2)]
+    for cy, cx in centres:
+        size = core + 2 * margin
+        wo = _window(w, cy, cx, size)
+        Eo, Bo, _ = run_oracle(wo, nsteps)
+        wo2 = _window(w, cy, cx, size + 64)
+        Eo2, Bo2, _ = run_oracle(wo2, nsteps)
+        s0 = slice(margin, margin + core)
+        s2 = slice(margin + 32, margin + 32 + core)
+        # the dependency cone stays inside the margin
+        cone = rel_err([a[s2, s2] for a in Eo2 + Bo2], [a[s0, s0] for a in Eo + Bo])
+        assert max(cone) < 1e-13, (cy, cx, cone)
+        rows = (cy - size // 2 + np.arange(size))[s0] % n
+        cols = (cx - size // 2 + np.arange(size))[s0] % n
+        for dt_, tol, (Eg, Bg, _, _) in runs:
+            got = [a[np.ix_(rows, cols)] for a in Eg + Bg]
+            e = rel_err(got, [a[s0, s0] for a in Eo + Bo])
+            log(f"window at ({cy}, {cx}): {dt_} GPU vs FP64 oracle {max(e):.2e}")
+            assert max(e) < tol, (dt_, cy, cx, e)
