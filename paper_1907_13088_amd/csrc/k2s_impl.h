@@ -289,7 +289,7 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
                             st_off(a.x_out[q], o, nv[q]);
                             if (DELTA) st_off(a.s_out[q], o, nc[q]);
                         }
-                        if (last) st_off(a.E[q], o, pe[ps][q] + (DELTA ? nc[q] : nv[q]));
+                        if (last) st_off_nt(a.E[q], o, pe[ps][q] + (DELTA ? nc[q] : nv[q]));
                     }
                 }
             }

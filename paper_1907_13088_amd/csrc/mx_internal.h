@@ -94,6 +94,14 @@ __device__ __forceinline__ void st_off(T *base, unsigned byte_off, T v)
     *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
 }
 
+// Store that is not kept in the caches (non-temporal): for results that no
+// kernel reads again soon, such as E at the end of a step
+template <typename T>
+__device__ __forceinline__ void st_off_nt(T *base, unsigned byte_off, T v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off));
+}
+
 // One grid of a batch (device-resident descriptor)
 template <typename T>
 struct GridDesc {
