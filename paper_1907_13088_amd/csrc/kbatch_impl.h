@@ -105,10 +105,15 @@ __device__ __forceinline__ bool grid_barrier(unsigned *bar, unsigned nblocks, in
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
+        // release fence + relaxed arrival: one L2 write-back per workgroup
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned prev = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned prev = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (prev == nblocks - 1) {
+            // the last arriver read every arrival: it acquires them before it
+            // releases the next generation (so the chain of releases reaches
+            // every waiter's acquire)
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&bar[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
