@@ -12,6 +12,9 @@
  *                           matrixA_1st..matrixA_last (3D) and
  *                           matrixA_1st_2d..matrixA_last_2d (2D)
  *   fixed-point solve ..... Alg 1 (Sec. 2.2.1)
+ *   accelerated solve ..... optional Chebyshev semi-iteration on each 2D
+ *                           block's spectral interval (the paper names faster
+ *                           solves as future work; see ora_solve)
  *   E increment ........... E^{n+1} = E^n + dE (Sec. 2.2.1)
  *   low-pass filter ....... applied to the current (Sec. 4.2, Sec. 5); the
  *                           paper gives no stencil, the reading taken is p
@@ -41,6 +44,7 @@ typedef struct {
     int filter_passes;   /* p */
     int lumped;          /* all averaging operators -> 1: the Yee scheme */
     double four_pi;      /* source constant */
+    int solver;          /* 0: Alg 1; 1: Chebyshev semi-iteration (see ora_solve) */
 } ora_cfg;
 
 typedef struct {
@@ -298,6 +302,76 @@ static double norm2_mask(const ora_cfg *c, double *const a[3], double *const b[3
 }
 
 /* ------------------------------------------------------------------------ */
+/* Upper end of the spectrum of A on block b (its lower end is 0): the       */
+/* largest eigenvalue of the Fourier symbol of A over the Brillouin zone.    */
+/* With s_i = sin^2(k_i d_i/2) the 2D TM symbol is                           */
+/*   (2/3)(1-rx) sx + (2/3)(1-ry) sy - (4/9)(1-rx-ry) sx sy,                 */
+/* bilinear in (sx, sy), so its maximum is at a corner of [0,1]^2; the 2D TE */
+/* symbol is the 2x2 matrix [[(2/3)(1-ry) sy, m], [m, (2/3)(1-rx) sx]] with  */
+/* m^2 = (4/9) rx ry sx sy, whose largest eigenvalue peaks at sx = sy = 1,   */
+/* where it is 2/3 for any dt.                                               */
+/* ------------------------------------------------------------------------ */
+static double spectrum_top(const ora_cfg *c, int blk)
+{
+    double rx = c->dt * c->dt / (c->dx * c->dx), ry = c->dt * c->dt / (c->dy * c->dy);
+    if (blk == 0) return 2.0 / 3.0;
+    double a = 2.0 / 3.0 * (1.0 - rx), b = 2.0 / 3.0 * (1.0 - ry), d = 8.0 / 9.0 - 2.0 / 9.0 * (rx + ry);
+    double m = a > b ? a : b;
+    return m > d ? m : d;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Chebyshev semi-iteration for (1 - A) x = b on one block, an accelerated  */
+/* alternative to Alg 1 (the paper leaves faster solves to future work).     */
+/* 1 - A is symmetric with its spectrum in [1 - rho, 1]; theta and delta are */
+/* the centre and half width of that interval, s1 = theta/delta.  Starting   */
+/* from x_0 = b, sweep k (k = 0, 1, ...) takes                               */
+/*   r_k = b + A x_k - x_k                   (the residual of x_k)           */
+/*   w_0 = 1/s1,  d_0 = r_0/theta                                            */
+/*   w_k = 1/(2 s1 - w_(k-1)),  d_k = w_k w_(k-1) d_(k-1) + (2 w_k/delta) r_k */
+/*   x_(k+1) = x_k + d_k,                                                    */
+/* the three-term recurrence of the Chebyshev polynomials written with the  */
+/* increments d_k.  After j sweeps x holds x_j; a tolerance stop tests       */
+/* ||r_(j-1)|| <= tol ||b|| at the check points, as Alg 1 tests             */
+/* ||x_j - x_(j-1)||, which is the same residual.                            */
+/* ------------------------------------------------------------------------ */
+static void solve_cheb_block(const ora_cfg *c, double *const b[3], double *x[3], int mask, int target,
+                             int use_tol, double bn, double *tmp[3], double *d[3], int *jout, double *rout)
+{
+    long n = ncell(c);
+    double rho = spectrum_top(c, mask == 4 ? 1 : 0);
+    double theta = 1.0 - rho / 2.0, delta = rho / 2.0, s1 = theta / delta;
+    double w_prev = 0.0;
+    int j = 0;
+    double res = 0.0;
+    while (j < target) {
+        ora_apply_A(c, x, tmp, mask);
+        double w, cd, cr;
+        if (j == 0) { w = 1.0 / s1; cd = 0.0; cr = 1.0 / theta; }
+        else { w = 1.0 / (2.0 * s1 - w_prev); cd = w * w_prev; cr = 2.0 * w / delta; }
+        w_prev = w;
+        double s = 0.0;
+        for (int q = 0; q < 3; q++) {
+            if (!(mask & (1 << q))) continue;
+            for (long o = 0; o < n; o++) {
+                double r = b[q][o] + tmp[q][o] - x[q][o];
+                s += r * r;
+                d[q][o] = cd * d[q][o] + cr * r;
+                x[q][o] += d[q][o];
+            }
+        }
+        res = sqrt(s);
+        j++;
+        if (use_tol) {
+            int g = c->check_every > 0 ? c->check_every : 1;
+            if ((j % g == 0 || j == target) && res <= c->tol * bn) break;
+        }
+    }
+    *jout = j;
+    *rout = res;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Alg 1: x_(0) = b; x_(j+1) = b + A x_(j).  Per decoupled block: a fixed   */
 /* count (tol == 0 or replay given), or stop after sweep j+1 when it is a   */
 /* check point and ||x_(j+1) - x_(j)|| <= tol ||b||, or at m_max.  When     */
@@ -326,6 +400,12 @@ void ora_solve(const ora_cfg *c, double *const b[3], double *x[3], const int *re
         if (!replay && c->tol > 0.0 && bn == 0.0) target = 0;
         int j = 0;
         double res = 0.0;
+        if (c->solver == 1) {
+            for (int q = 0; q < 3; q++)
+                if (mask & (1 << q)) memset(nx_[q], 0, sizeof(double) * n);
+            solve_cheb_block(c, b, x, mask, target, !replay && c->tol > 0.0, bn, tmp, nx_, &j, &res);
+            target = 0;   /* done: skip the Alg 1 loop */
+        }
         while (j < target) {
             ora_apply_A(c, x, tmp, mask);
             for (int q = 0; q < 3; q++) {

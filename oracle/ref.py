@@ -34,7 +34,7 @@ class _Cfg(C.Structure):
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double), ("dt", C.c_double),
                 ("blocks", C.c_int), ("sweeps", C.c_int), ("tol", C.c_double),
                 ("check_every", C.c_int), ("filter_passes", C.c_int), ("lumped", C.c_int),
-                ("four_pi", C.c_double)]
+                ("four_pi", C.c_double), ("solver", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -77,8 +77,11 @@ class Config:
     filter_passes: int = 0
     lumped: bool = False
     four_pi: float = 4.0 * math.pi
+    solver: int = 0                 # 0: Alg 1; 1: Chebyshev semi-iteration
 
     def c(self) -> _Cfg:
+        if self.solver != 0 and self.ndim != 2:
+            raise ValueError("the Chebyshev solve is defined for 2D grids only")
         if self.ndim == 2:
             ny, nx = self.shape
             nz = 1
@@ -86,7 +89,8 @@ class Config:
             nz, ny, nx = self.shape
         d = list(self.d) + [1.0] * (3 - len(self.d))
         return _Cfg(self.ndim, nx, ny, nz, d[0], d[1], d[2], self.dt, self.blocks, self.sweeps,
-                    self.tol, self.check_every, self.filter_passes, int(self.lumped), self.four_pi)
+                    self.tol, self.check_every, self.filter_passes, int(self.lumped), self.four_pi,
+                    int(self.solver))
 
 
 def _p3(arrs):

@@ -637,3 +637,90 @@ def test_adjoint_te_source_has_zero_ez_gradient():
         ref.adjoint_step(cfg, Eb, Bb, Jb, 0.9, (3, 3))
     assert np.abs(Jb[0]).max() == 0.0 and np.abs(Jb[1]).max() == 0.0
     assert np.abs(Jb[2]).max() > 0.0
+
+
+# --- Chebyshev semi-iteration (an accelerated alternative to Alg 1) --------
+
+def _cheb_top(dt, d, blk):
+    """Largest eigenvalue of the 2D block symbol over the Brillouin zone
+    (TE: 2/3; TM: the largest corner value of the bilinear symbol)."""
+    rx, ry = dt * dt / (d[0] * d[0]), dt * dt / (d[1] * d[1])
+    if blk == 0:
+        return 2.0 / 3.0
+    return max(2 / 3 * (1 - rx), 2 / 3 * (1 - ry), 8 / 9 - 2 / 9 * (rx + ry))
+
+
+@pytest.mark.parametrize("dt_frac,d", [(0.5, (1.0, 1.0)), (0.9, (1.0, 1.0)), (0.7, (1.0, 0.6)), (0.3, (0.8, 1.0))])
+def test_A_2d_block_spectrum_spans_zero_to_symbol_top(dt_frac, d):
+    """On an even grid (whose lattice holds the Brillouin-zone corners) the
+    eigenvalues of the assembled A fill [0, rho] per block: rho is 2/3 for
+    TE at any dt and the largest corner value of the bilinear symbol for TM."""
+    dt = dt_frac * S_cfl(d)
+    cfg = ref.Config(ndim=2, shape=(6, 8), dt=dt, d=d)
+    for blk, mask in ((0, 3), (1, 4)):
+        ev = np.linalg.eigvalsh(assemble_A(cfg, mask))
+        assert ev.min() > -1e-13
+        assert abs(ev.max() - _cheb_top(dt, d, blk)) < 1e-13
+
+
+def _cheb_polynomial_iterate(M, b, k, rho):
+    """x_k of the Chebyshev method from x_0 = b, written from its error
+    polynomial: e_k = T_k((theta - B)/delta) e_0 / T_k(theta/delta) with
+    B = 1 - A on [1 - rho, 1], evaluated in the eigenbasis of A."""
+    lam, Q = np.linalg.eigh(M)
+    theta, delta = 1 - rho / 2, rho / 2
+    xs = Q @ ((Q.T @ b) / (1 - lam))
+    e0 = Q.T @ (xs - b)
+    Tk = np.polynomial.chebyshev.chebval((theta - (1 - lam)) / delta, [0] * k + [1])
+    Tk0 = np.polynomial.chebyshev.chebval(theta / delta, [0] * k + [1])
+    return xs - Q @ (Tk / Tk0 * e0)
+
+
+def test_chebyshev_iterates_are_the_chebyshev_polynomials():
+    """The oracle's three-term recurrence after k sweeps equals the Chebyshev
+    error polynomial applied to the initial error (each block on its own
+    interval), for several k; and with a tolerance it reaches the direct
+    solve in far fewer sweeps than Alg 1."""
+    rng = np.random.default_rng(17)
+    shape, d = (6, 5), (1.0, 1.0)
+    dt = 0.5 * S_cfl(d)
+    b = [rng.normal(size=shape) for _ in range(3)]
+    for blk, mask, comps in ((0, 3, (0, 1)), (1, 4, (2,))):
+        M = assemble_A(ref.Config(ndim=2, shape=shape, dt=dt, d=d), mask)
+        bv = np.concatenate([b[q].ravel() for q in comps])
+        for k in (1, 2, 5, 13):
+            cfg = ref.Config(ndim=2, shape=shape, dt=dt, d=d, blocks=1 << blk, sweeps=k, solver=1)
+            x, st = ref.solve(cfg, b)
+            xv = np.concatenate([x[q].ravel() for q in comps])
+            want = _cheb_polynomial_iterate(M, bv, k, _cheb_top(dt, d, blk))
+            assert np.abs(xv - want).max() < 1e-12 * np.abs(want).max(), (blk, k)
+            assert st.sweeps[blk] == k
+    I = np.eye(3 * shape[0] * shape[1])
+    M = assemble_A(ref.Config(ndim=2, shape=shape, dt=dt, d=d), 7)
+    direct = np.linalg.solve(I - M, np.concatenate([q.ravel() for q in b]))
+    counts = {}
+    for solver in (0, 1):
+        cfg = ref.Config(ndim=2, shape=shape, dt=dt, d=d, blocks=3, sweeps=400, tol=1e-12, solver=solver)
+        x, st = ref.solve(cfg, b)
+        xv = np.concatenate([q.ravel() for q in x])
+        assert np.abs(xv - direct).max() < 1e-10 * np.abs(direct).max()
+        counts[solver] = st.sweeps
+    # rates: Alg 1 rho per sweep; Chebyshev (sqrt(k) - 1)/(sqrt(k) + 1), k = 1/(1 - rho)
+    assert counts[1][0] < 0.5 * counts[0][0] and counts[1][1] < 0.5 * counts[0][1], counts
+
+
+def test_chebyshev_error_bound():
+    """||e_k||_2 <= ||e_0||_2 / T_k(theta/delta) (the minimax property)."""
+    rng = np.random.default_rng(19)
+    shape, d = (8, 6), (1.0, 0.7)
+    dt = 0.8 * S_cfl(d)
+    M = assemble_A(ref.Config(ndim=2, shape=shape, dt=dt, d=d), 4)
+    b = [np.zeros(shape), np.zeros(shape), rng.normal(size=shape)]
+    xs = np.linalg.solve(np.eye(M.shape[0]) - M, b[2].ravel())
+    rho = _cheb_top(dt, d, 1)
+    theta, delta = 1 - rho / 2, rho / 2
+    e0 = np.linalg.norm(xs - b[2].ravel())
+    for k in (3, 8, 20):
+        x, _ = ref.solve(ref.Config(ndim=2, shape=shape, dt=dt, d=d, blocks=2, sweeps=k, solver=1), b)
+        bound = e0 / np.polynomial.chebyshev.chebval(theta / delta, [0] * k + [1])
+        assert np.linalg.norm(x[2].ravel() - xs) <= bound * (1 + 1e-9)
