@@ -66,6 +66,19 @@ extern "C" {
 #define MX_FORM_STANDARD 0
 #define MX_FORM_DELTA    1
 
+/* solve of the mass-matrix system (1 - A) dE = dE' (eq transform-e-e_aux):
+   ALG1 is the paper's fixed-point iteration (Alg 1, Sec. 2.2.1); CHEBYSHEV
+   is the Chebyshev semi-iteration on each 2D block's spectral interval of
+   1 - A, [1 - rho, 1] with rho = 2/3 (TE) and the largest corner value of
+   the TM symbol, an accelerated solve the paper names as future work
+   (Sec. 2.2.1).  It counts sweeps like Alg 1 (one application of A each)
+   and its tolerance test uses the same residual ||dE' + A x - x||_2, but
+   its iterates differ: it reaches a given residual in far fewer sweeps.
+   2D row streaming only (variants 0, 2, 3), standard form, not lumped; no
+   batch or adjoint. */
+#define MX_SOLVER_ALG1      0
+#define MX_SOLVER_CHEBYSHEV 1
+
 /* init-time warnings (bit flags) */
 #define MX_WARN_NOCONV_GUARANTEE 1  /* 3D, dt > min(d)/sqrt(2): the infinity-norm
                                        convergence bound of Appendix C does not hold */
@@ -95,6 +108,9 @@ typedef struct mx_config {
                              1 LDS tile (both blocks per pass), 2 row streaming
                              (both blocks per pass), 3 row streaming (each block
                              on its own) */
+    int solver;           /* MX_SOLVER_ALG1 (default) or MX_SOLVER_CHEBYSHEV; the
+                             Chebyshev passes fuse at most: both blocks 5 (FP32),
+                             2 (FP64); TE 8, 3; TM 12, 6 */
 } mx_config;
 
 typedef struct mx_step_stats {

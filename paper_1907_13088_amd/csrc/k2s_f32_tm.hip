@@ -3,7 +3,7 @@
 
 namespace mx {
 namespace stream2d {
-template hipError_t launch<float, false, 2>(const Coef<float> &, int, int, const SweepArgs<float> &, hipStream_t,
+template hipError_t launch<float, FM_STD, 2>(const Coef<float> &, int, int, const SweepArgs<float> &, hipStream_t,
                                            int *, int);
 }  // namespace stream2d
 }  // namespace mx

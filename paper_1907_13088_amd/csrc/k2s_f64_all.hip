@@ -3,7 +3,7 @@
 
 namespace mx {
 namespace stream2d {
-template hipError_t launch<double, false, 3>(const Coef<double> &, int, int, const SweepArgs<double> &, hipStream_t,
+template hipError_t launch<double, FM_STD, 3>(const Coef<double> &, int, int, const SweepArgs<double> &, hipStream_t,
                                            int *, int);
 }  // namespace stream2d
 }  // namespace mx

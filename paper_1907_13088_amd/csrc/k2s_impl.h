@@ -87,11 +87,12 @@ constexpr size_t stream_lds_bytes() { return sizeof(T) * (size_t)K * 2 * stream_
 
 // One work item: strip wid % nsx, chunk wid / nsx of rows [Y0, Y0 + L).
 // pidx is where the item's FP64 partial sums go (OM_RESID only).
-template <typename T, int BLK, int K, bool DELTA, int RX, int OM>
+template <typename T, int BLK, int K, int FORM, int RX, int OM>
 __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T> &a, int flags, int L, int nsx,
                                             int wid, int pidx, void *lds, double *sred)
 {
     constexpr bool TE = BLK & 1, TM = BLK & 2;
+    constexpr bool DELTA = FORM == FM_DELTA, CHEB = FORM == FM_CHEB;
     constexpr int H = stream_halo(K);          // columns left of the first output column
     constexpr int W = stream_width<RX>(K);
     static_assert(H >= K && RX - H - W >= K, "the halo must cover every level");
@@ -120,12 +121,14 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
     T wex[K + 1][3], wez[K + 1][3], wg[K + 1][3], wlx[K + 1][3];
     T wley[K + 1][2], wh[K + 1][2], wey[K + 1][2];
     T wc[K + 1][2][3];
+    T wd[K + 1][2][3];   // Chebyshev form: the carried increment, like wc
 #pragma unroll
     for (int l = 0; l <= K; l++)
 #pragma unroll
         for (int q = 0; q < 3; q++) {
             out[l][q] = wex[l][q] = wez[l][q] = wg[l][q] = wlx[l][q] = T(0);
             wc[l][0][q] = wc[l][1][q] = T(0);
+            wd[l][0][q] = wd[l][1][q] = T(0);
             if (q < 2) wley[l][q] = wh[l][q] = wey[l][q] = T(0);
         }
 
@@ -133,11 +136,11 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
     // (in the unrolled steady state the shifts are register renaming)
     constexpr int PF = stream_pf<T, BLK, K>();
     static_assert(6 % PF == 0, "the unrolled group of 6 steps must cycle the FIFO");
-    T px[PF][3], pc[PF][3], pe[PF][3];
+    T px[PF][3], pc[PF][3], pe[PF][3], pd[PF][3];
 #pragma unroll
     for (int u = 0; u < PF; u++)
 #pragma unroll
-        for (int q = 0; q < 3; q++) px[u][q] = pc[u][q] = pe[u][q] = T(0);
+        for (int q = 0; q < 3; q++) px[u][q] = pc[u][q] = pe[u][q] = pd[u][q] = T(0);
     // uniform bases of the level-0 iterate and of the carried quantity (on the
     // first pass both are dE': the second read of a row hits the cache)
     const T *xb[3], *cb[3];
@@ -146,6 +149,8 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
         xb[q] = first ? a.rhs[q] : a.x_in[q];
         cb[q] = (DELTA && !first) ? a.s_in[q] : a.rhs[q];
     }
+    // Chebyshev form: the increment of the input iterate (zero before the
+    // first sweep; s_in is then any valid buffer and its values are unused)
     // byte offset of the next level-0 row to load, advanced with a wrap
     // (a uniform scalar), plus the thread's column
     const unsigned rowb = (unsigned)nx * (unsigned)sizeof(T);
@@ -153,13 +158,14 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
     const unsigned colb = (unsigned)gx * (unsigned)sizeof(T);
     const int tbeg = Y0 - K, tend = Y0 + L + 2 * K;
     unsigned lo = (unsigned)wrapi(tbeg, ny) * rowb;
-    auto load_row = [&](T(&x)[3], T(&cc)[3]) {
+    auto load_row = [&](T(&x)[3], T(&cc)[3], T(&dd)[3]) {
         const unsigned o = lo + colb;
 #pragma unroll
         for (int q = 0; q < 3; q++) {
             if ((q < 2 && !TE) || (q == 2 && !TM)) continue;
             x[q] = ld_off(xb[q], o);
             cc[q] = ld_off(cb[q], o);
+            if (CHEB) dd[q] = ld_off(a.s_in[q], o);
         }
         lo += rowb;
         if (lo >= allb) lo -= allb;
@@ -178,7 +184,7 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
     // head of the FIFO
 #pragma unroll
     for (int u = 0; u < PF; u++) {
-        load_row(px[u], pc[u]);
+        load_row(px[u], pc[u], pd[u]);
         load_e(tbeg + u - 2 * K, pe[u]);
     }
     double rte = 0.0, rtm = 0.0;
@@ -227,6 +233,10 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
                 }
 #pragma unroll
                 for (int q = 0; q < 3; q++) { wc[l][0][q] = wc[l][1][q]; wc[l][1][q] = wc[l - 1][0][q]; }
+                if (CHEB) {
+#pragma unroll
+                    for (int q = 0; q < 3; q++) { wd[l][0][q] = wd[l][1][q]; wd[l][1][q] = wd[l - 1][0][q]; }
+                }
             }
             // row t-2l of level l
             const int r = t - 2 * l;
@@ -258,12 +268,27 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
                         nc[2] = wc[l][0][2] + nv[2];
                     }
                 }
+                // Chebyshev form: nv holds b + A x; the residual r = nv - x
+                // updates the increment d and the iterate x + d
+                T rr[3] = {T(0), T(0), T(0)}, nd[3] = {T(0), T(0), T(0)};
+                if (CHEB) {
+                    const T xo[3] = {wex[l][1], wey[l][0], wez[l][1]};
+#pragma unroll
+                    for (int q = 0; q < 3; q++) {
+                        if ((q < 2 && !TE) || (q == 2 && !TM)) continue;
+                        const int bk = q < 2 ? 0 : 1;
+                        rr[q] = nv[q] - xo[q];
+                        nd[q] = fmad(a.cheb[bk][0][l - 1], wd[l][0][q], a.cheb[bk][1][l - 1] * rr[q]);
+                        nv[q] = xo[q] + nd[q];
+                    }
+                }
                 if (l < K) {
 #pragma unroll
                     for (int q = 0; q < 3; q++) {
                         if ((q < 2 && !TE) || (q == 2 && !TM)) continue;
                         out[l][q] = nv[q];
                         wc[l][0][q] = nc[q];   // carried value of this row, read by level l+1 next step
+                        if (CHEB) wd[l][0][q] = nd[q];
                     }
                     if (BOTH) *reinterpret_cast<Triple<T> *>(&xq[l][pw][i + 1]) = Triple<T>{nv[1], nv[2], nv[0]};
                     else if (TE) xp[l][pw][i + 1] = Pair<T>{nv[0], nv[1]};
@@ -273,12 +298,12 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
                     const unsigned o = (unsigned)(r * nx + gxi) * (unsigned)sizeof(T);
                     if (resid) {
                         if (TE) {
-                            const double d0 = DELTA ? (double)nv[0] : (double)nv[0] - (double)wex[l][1];
-                            const double d1 = DELTA ? (double)nv[1] : (double)nv[1] - (double)wey[l][0];
+                            const double d0 = CHEB ? (double)rr[0] : DELTA ? (double)nv[0] : (double)nv[0] - (double)wex[l][1];
+                            const double d1 = CHEB ? (double)rr[1] : DELTA ? (double)nv[1] : (double)nv[1] - (double)wey[l][0];
                             rte += d0 * d0 + d1 * d1;
                         }
                         if (TM) {
-                            const double d2 = DELTA ? (double)nv[2] : (double)nv[2] - (double)wez[l][1];
+                            const double d2 = CHEB ? (double)rr[2] : DELTA ? (double)nv[2] : (double)nv[2] - (double)wez[l][1];
                             rtm += d2 * d2;
                         }
                     }
@@ -288,6 +313,7 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
                         if (store) {
                             st_off(a.x_out[q], o, nv[q]);
                             if (DELTA) st_off(a.s_out[q], o, nc[q]);
+                            if (CHEB) st_off(a.s_out[q], o, nd[q]);
                         }
                         if (last) st_off_nt(a.E[q], o, pe[ps][q] + (DELTA ? nc[q] : nv[q]));
                     }
@@ -301,6 +327,7 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
                 if ((q < 2 && !TE) || (q == 2 && !TM)) continue;
                 out[0][q] = px[ps][q];
                 wc[0][0][q] = pc[ps][q];
+                if (CHEB) wd[0][0][q] = first ? T(0) : pd[ps][q];
             }
             if (BOTH) *reinterpret_cast<Triple<T> *>(&xq[0][pw][i + 1]) = Triple<T>{px[ps][1], px[ps][2], px[ps][0]};
             else if (TE) xp[0][pw][i + 1] = Pair<T>{px[ps][0], px[ps][1]};
@@ -310,8 +337,8 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
 #pragma unroll
             for (int u = 0; u + 1 < PF; u++)
 #pragma unroll
-                for (int q = 0; q < 3; q++) { px[u][q] = px[u + 1][q]; pc[u][q] = pc[u + 1][q]; }
-            if (ALL || t + PF < Y0 + L + K) load_row(px[PF - 1], pc[PF - 1]);
+                for (int q = 0; q < 3; q++) { px[u][q] = px[u + 1][q]; pc[u][q] = pc[u + 1][q]; pd[u][q] = pd[u + 1][q]; }
+            if (ALL || t + PF < Y0 + L + K) load_row(px[PF - 1], pc[PF - 1], pd[PF - 1]);
         }
         if (last) {
 #pragma unroll
@@ -351,17 +378,17 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
     lds_barrier();   // the LDS rows are reused by the caller's next item
 }
 
-template <typename T, int BLK, int K, bool DELTA, int RX, int OM>
+template <typename T, int BLK, int K, int FORM, int RX, int OM>
 __global__ __launch_bounds__(RX) void k2_stream(Coef<T> c, SweepArgs<T> a, int flags, int L, int nsx, int nwg)
 {
     __shared__ __attribute__((aligned(16))) char lds[stream_lds_bytes<T, BLK, K, RX>()];
     __shared__ double sred[2 * RX / 64];
-    stream_tile<T, BLK, K, DELTA, RX, OM>(c, a, flags, L, nsx, xcd_map(blockIdx.x, nwg), blockIdx.x, lds, sred);
+    stream_tile<T, BLK, K, FORM, RX, OM>(c, a, flags, L, nsx, xcd_map(blockIdx.x, nwg), blockIdx.x, lds, sred);
 }
 
 constexpr int SRX = 256;   // threads (columns) per workgroup strip
 
-template <typename T, int BLK, int K, bool DELTA, int OM>
+template <typename T, int BLK, int K, int FORM, int OM>
 hipError_t stream_om(const Coef<T> &c, int flags, const SweepArgs<T> &a, hipStream_t s, int *nwg, int slots)
 {
     constexpr int W = stream_width<SRX>(K);
@@ -369,7 +396,7 @@ hipError_t stream_om(const Coef<T> &c, int flags, const SweepArgs<T> &a, hipStre
     if (occ < 0) {
         int o = 0, dev = 0, cu = 0;
         (void)hipGetDevice(&dev);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k2_stream<T, BLK, K, DELTA, SRX, OM>, SRX, 0) != hipSuccess || o < 1) o = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k2_stream<T, BLK, K, FORM, SRX, OM>, SRX, 0) != hipSuccess || o < 1) o = 1;
         if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu < 1) cu = 256;
         ncu = cu;
         occ = o;
@@ -385,46 +412,51 @@ hipError_t stream_om(const Coef<T> &c, int flags, const SweepArgs<T> &a, hipStre
     nsy = (c.ny + L - 1) / L;
     const int n = nsx * nsy;
     *nwg = n;
-    hipLaunchKernelGGL((k2_stream<T, BLK, K, DELTA, SRX, OM>), dim3(n), dim3(SRX), 0, s, c, a, flags, L, nsx, n);
+    hipLaunchKernelGGL((k2_stream<T, BLK, K, FORM, SRX, OM>), dim3(n), dim3(SRX), 0, s, c, a, flags, L, nsx, n);
     return hipGetLastError();
 }
 
-template <typename T, int BLK, int K, bool DELTA>
+template <typename T, int BLK, int K, int FORM>
 hipError_t stream_k(const Coef<T> &c, int flags, const SweepArgs<T> &a, hipStream_t s, int *nwg, int slots)
 {
     const int out = flags & (SW_LAST | SW_STORE | SW_RESID);
-    if (out == SW_LAST) return stream_om<T, BLK, K, DELTA, OM_LAST>(c, flags, a, s, nwg, slots);
-    if (out == SW_STORE) return stream_om<T, BLK, K, DELTA, OM_STORE>(c, flags, a, s, nwg, slots);
-    if (out == (SW_STORE | SW_RESID)) return stream_om<T, BLK, K, DELTA, OM_RESID>(c, flags, a, s, nwg, slots);
+    if (out == SW_LAST) return stream_om<T, BLK, K, FORM, OM_LAST>(c, flags, a, s, nwg, slots);
+    if (out == SW_STORE) return stream_om<T, BLK, K, FORM, OM_STORE>(c, flags, a, s, nwg, slots);
+    if (out == (SW_STORE | SW_RESID)) return stream_om<T, BLK, K, FORM, OM_RESID>(c, flags, a, s, nwg, slots);
     return hipErrorInvalidValue;
 }
 
 // deepest pass (sweeps per pass) of a block set's kernel: the per-level
 // register windows must leave two waves per SIMD (TE carries 2 components,
-// TM one, both together 3)
-template <typename T, int BLK, bool DELTA>
+// TM one, both together 3; the Chebyshev form carries one more value per
+// component and level)
+template <typename T, int BLK, int FORM>
 constexpr int stream_kmax()
 {
+    if (FORM == FM_CHEB)
+        return sizeof(T) == 4 ? (BLK == 1 ? 8 : BLK == 2 ? 12 : 5) : (BLK == 1 ? 3 : BLK == 2 ? 6 : 2);
+    constexpr bool DELTA = FORM == FM_DELTA;
     return sizeof(T) == 4 ? (BLK == 1 ? (DELTA ? 9 : 10) : BLK == 2 ? 16 : (DELTA ? 6 : 7)) : (BLK == 1 ? (DELTA ? 4 : 5) : BLK == 2 ? 8 : 3);
 }
 
-template <typename T, int BLK, bool DELTA, int K>
+template <typename T, int BLK, int FORM, int K>
 hipError_t stream_kdisp(const Coef<T> &c, int k, int flags, const SweepArgs<T> &a, hipStream_t s, int *nwg,
                         int slots)
 {
     if constexpr (K == 0) {
         return hipErrorInvalidValue;
     } else {
-        if (k == K) return stream_k<T, BLK, K, DELTA>(c, flags, a, s, nwg, slots);
-        return stream_kdisp<T, BLK, DELTA, K - 1>(c, k, flags, a, s, nwg, slots);
+        if (k == K) return stream_k<T, BLK, K, FORM>(c, flags, a, s, nwg, slots);
+        return stream_kdisp<T, BLK, FORM, K - 1>(c, k, flags, a, s, nwg, slots);
     }
 }
 
-// one pass of k sweeps over the TE (BLK 1) or the TM (BLK 2) block, or both (3)
-template <typename T, bool DELTA, int BLK>
+// one pass of k sweeps over the TE (BLK 1) or the TM (BLK 2) block, or both
+// (3), in iterate form FORM
+template <typename T, int FORM, int BLK>
 hipError_t launch(const Coef<T> &c, int k, int flags, const SweepArgs<T> &a, hipStream_t s, int *nwg, int slots)
 {
-    return stream_kdisp<T, BLK, DELTA, stream_kmax<T, BLK, DELTA>()>(c, k, flags, a, s, nwg, slots);
+    return stream_kdisp<T, BLK, FORM, stream_kmax<T, BLK, FORM>()>(c, k, flags, a, s, nwg, slots);
 }
 
 }  // namespace stream2d

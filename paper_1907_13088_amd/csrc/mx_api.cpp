@@ -77,8 +77,9 @@ void pass_depths(const mx_config *c, int variant, int out[2])
     }
     const bool tolmode = c->tol > 0.0;
     const bool delta = tolmode && c->form == MX_FORM_DELTA;
+    const int form = c->solver == MX_SOLVER_CHEBYSHEV ? mx::FM_CHEB : delta ? mx::FM_DELTA : mx::FM_STD;
     const bool joint = variant == 2 && c->blocks == MX_ALL;
-    const int kmax[2] = {mx::stream2d_kmax(f64, joint ? 3 : 1, delta), mx::stream2d_kmax(f64, joint ? 3 : 2, delta)};
+    const int kmax[2] = {mx::stream2d_kmax(f64, joint ? 3 : 1, form), mx::stream2d_kmax(f64, joint ? 3 : 2, form)};
     for (int b = 0; b < 2; b++) {
         int k = c->sweeps_per_pass > 0 ? c->sweeps_per_pass : kmax[b];
         if (tolmode && c->sweeps_per_pass <= 0) k = std::min(kmax[0], kmax[1]);
@@ -90,8 +91,10 @@ void pass_depths(const mx_config *c, int variant, int out[2])
 int n_arrays(const mx_config *c)
 {
     // dE' (3), two iterate buffers (6), running sum (3), then
-    // 2D: a second B buffer (3); 3D: filtered current and a filter temp (6)
-    return c->ndim == 2 ? 15 : 18;
+    // 2D: a second B buffer (3), and for the Chebyshev solve a second
+    // increment buffer (3); 3D: filtered current and a filter temp (6)
+    if (c->ndim == 2) return c->solver == MX_SOLVER_CHEBYSHEV ? 18 : 15;
+    return 18;
 }
 
 }  // namespace
@@ -112,6 +115,7 @@ struct mx_grid {
     void *E[3], *B[3], *J0[3];
     bool bound, has_j;
     void *dEp[3], *X[2][3], *S[3], *Bws[3], *Jf[3], *Jt[3];
+    void *D2[3];          // Chebyshev solve: the increment buffer paired with S
     int bloc[3];          // 2D: where component q of B currently lives (0 user, 1 workspace)
     double *partial;      // device
     double *red;          // device, 2 doubles
@@ -120,6 +124,9 @@ struct mx_grid {
                           // together), 3 row streaming (each block on its own)
     Coef<float> cf;
     Coef<double> cd;
+    // Chebyshev solve: per block, the factors (previous increment, residual)
+    // of sweep k, for k < cfg.sweeps
+    std::vector<double> cheb[2][2];
     // timing (mx_profile_*)
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
@@ -161,6 +168,42 @@ struct ProfScope {
 };
 
 }  // namespace
+
+// Chebyshev semi-iteration for (1 - A) x = b on a 2D block whose A has its
+// spectrum in [0, rho]: 1 - A lies in [1 - rho, 1], with centre theta and
+// half width delta, s1 = theta / delta.  Sweep k forms the residual
+// r_k = b + A x_k - x_k, the increment d_k = f_k d_(k-1) + g_k r_k and
+// x_(k+1) = x_k + d_k, where w_0 = 1/s1, f_0 = 0, g_0 = 1/theta and
+// w_k = 1/(2 s1 - w_(k-1)), f_k = w_k w_(k-1), g_k = 2 w_k / delta (the
+// three-term recurrence of the Chebyshev polynomials on that interval).
+// rho is the top of the block symbol over the Brillouin zone: 2/3 for TE at
+// any dt; for TM the largest corner value of the bilinear symbol
+// (2/3)(1-rx) sx + (2/3)(1-ry) sy - (4/9)(1-rx-ry) sx sy, s_i in [0, 1].
+static void fill_cheb(const mx_config *c, int n, std::vector<double> out[2][2])
+{
+    const double rx = c->dt * c->dt / (c->d[0] * c->d[0]), ry = c->dt * c->dt / (c->d[1] * c->d[1]);
+    const double rho[2] = {2.0 / 3.0, std::max({2.0 / 3.0 * (1.0 - rx), 2.0 / 3.0 * (1.0 - ry),
+                                                8.0 / 9.0 - 2.0 / 9.0 * (rx + ry)})};
+    n = std::max(n, 1);
+    for (int b = 0; b < 2; b++) {
+        const double theta = 1.0 - rho[b] / 2.0, delta = rho[b] / 2.0, s1 = theta / delta;
+        out[b][0].assign(n, 0.0);
+        out[b][1].assign(n, 0.0);
+        double wp = 0.0;
+        for (int k = 0; k < n; k++) {
+            if (k == 0) {
+                wp = 1.0 / s1;
+                out[b][0][0] = 0.0;
+                out[b][1][0] = 1.0 / theta;
+            } else {
+                const double w = 1.0 / (2.0 * s1 - wp);
+                out[b][0][k] = w * wp;
+                out[b][1][k] = 2.0 * w / delta;
+                wp = w;
+            }
+        }
+    }
+}
 
 template <typename T>
 static void fill_coef(const mx_config *c, Coef<T> &k)
@@ -237,6 +280,13 @@ int mx_validate(const mx_config *c, int *warn)
     if (c->lumped != 0 && c->lumped != 1) return fail(MX_EINVAL, "lumped must be 0 or 1");
     if (!std::isfinite(c->four_pi)) return fail(MX_EINVAL, "four_pi must be finite");
     if (c->form != MX_FORM_STANDARD && c->form != MX_FORM_DELTA) return fail(MX_EINVAL, "bad form");
+    if (c->solver != MX_SOLVER_ALG1 && c->solver != MX_SOLVER_CHEBYSHEV) return fail(MX_EINVAL, "bad solver");
+    if (c->solver == MX_SOLVER_CHEBYSHEV) {
+        if (c->ndim != 2) return fail(MX_EINVAL, "the Chebyshev solve is defined for 2D grids");
+        if (c->variant == 1) return fail(MX_EINVAL, "the Chebyshev solve runs on the row-streaming kernels (variant 0, 2 or 3)");
+        if (c->form != MX_FORM_STANDARD) return fail(MX_EINVAL, "the Chebyshev solve uses the standard form");
+        if (c->lumped) return fail(MX_EINVAL, "the lumped scheme has A = 0: no solve to accelerate");
+    }
     if (c->sweeps_per_pass < 0 || c->sweeps_per_pass > 16) return fail(MX_EINVAL, "sweeps_per_pass must be in [0, 16]");
     if (c->variant < 0 || c->variant > 3) return fail(MX_EINVAL, "variant must be 0, 1, 2 or 3");
     if (c->variant == 1 && c->sweeps_per_pass > 8)
@@ -305,9 +355,12 @@ int mx_init(const mx_config *cfg, void *stream, void *workspace, size_t workspac
     for (int b = 0; b < 2; b++)
         for (int q = 0; q < 3; q++) take(&g->X[b][q]);
     for (int q = 0; q < 3; q++) take(&g->S[q]);
+    for (int q = 0; q < 3; q++) g->D2[q] = nullptr;
     if (cfg->ndim == 2) {
         for (int q = 0; q < 3; q++) take(&g->Bws[q]);
         for (int q = 0; q < 3; q++) g->Jf[q] = g->Jt[q] = nullptr;
+        if (cfg->solver == MX_SOLVER_CHEBYSHEV)
+            for (int q = 0; q < 3; q++) take(&g->D2[q]);
     } else {
         for (int q = 0; q < 3; q++) take(&g->Jf[q]);
         for (int q = 0; q < 3; q++) take(&g->Jt[q]);
@@ -319,6 +372,7 @@ int mx_init(const mx_config *cfg, void *stream, void *workspace, size_t workspac
     for (int q = 0; q < 3; q++) { g->E[q] = g->B[q] = g->J0[q] = nullptr; g->bloc[q] = 0; }
     fill_coef(cfg, g->cf);
     fill_coef(cfg, g->cd);
+    if (cfg->solver == MX_SOLVER_CHEBYSHEV) fill_cheb(cfg, cfg->sweeps, g->cheb);
     *out = g;
     return MX_OK;
 }
@@ -438,6 +492,8 @@ int run_sweeps(mx_grid *g, void *const rhs[3], const int *target_in, bool tolmod
     const Coef<T> &k = coef<T>(g);
     const int nblk = c.ndim == 3 ? 1 : 2;
     const bool delta = c.form == MX_FORM_DELTA && tolmode;
+    const bool cheb = c.solver == MX_SOLVER_CHEBYSHEV;
+    const int form = cheb ? FM_CHEB : delta ? FM_DELTA : FM_STD;
     const bool split = c.ndim == 2 && g->variant == 3;
     int target[2] = {0, 0}, done[2] = {0, 0}, cur[2] = {-1, -1};
     bool conv[2] = {false, false}, fused[2] = {false, false};
@@ -447,6 +503,8 @@ int run_sweeps(mx_grid *g, void *const rhs[3], const int *target_in, bool tolmod
         active_cfg[b] = b < nblk && (c.ndim == 3 || (c.blocks & (1 << b)));
         target[b] = active_cfg[b] ? target_in[b] : 0;
     }
+    if (cheb && (int)g->cheb[0][0].size() < std::max(target[0], target[1]))
+        fill_cheb(&c, std::max(target[0], target[1]), g->cheb);
     const int groups[2] = {split ? 1 : 3, split ? 2 : 0};
     for (int gi = 0; gi < 2; gi++) {
         const int gmask = groups[gi];
@@ -486,6 +544,26 @@ int run_sweeps(mx_grid *g, void *const rhs[3], const int *target_in, bool tolmod
                 a.E[q] = E_fuse ? (T *)E_fuse[q] : nullptr;
             }
             a.partial = g->partial;
+            if (cheb) {
+                // increments ping-pong with the iterate (a pass reads its
+                // neighbours' halo increments, so none is updated in place);
+                // none before the first sweep: the kernel ignores the values
+                // it reads then, which hit the cache lines of dE'
+                void *const *Din = cb == 1 ? g->D2 : g->S;
+                void *const *Dout = ob == 1 ? g->D2 : g->S;
+                for (int q = 0; q < 3; q++) {
+                    a.s_in[q] = (const T *)(first ? rhs[q] : Din[q]);
+                    a.s_out[q] = (T *)Dout[q];
+                }
+                // factors of the pass's sweeps: level l runs sweep done[b] + l - 1
+                for (int b = 0; b < 2; b++)
+                    for (int l = 0; l < kk; l++) {
+                        const size_t ix = (size_t)(done[b] + l);
+                        const bool ok = ix < g->cheb[b][0].size();
+                        a.cheb[b][0][l] = (T)(ok ? g->cheb[b][0][ix] : 0.0);
+                        a.cheb[b][1][l] = (T)(ok ? g->cheb[b][1][ix] : 0.0);
+                    }
+            }
             int nwg = 0;
             hipError_t e;
             {
@@ -493,13 +571,14 @@ int run_sweeps(mx_grid *g, void *const rhs[3], const int *target_in, bool tolmod
                 // pass) with halo, dE' (standard form), the running sum (delta
                 // form), the stored iterate/sum, or E read and written
                 int arrs;
-                if (!delta) arrs = (first ? 1 : 2) + ((flags & SW_LAST) ? 2 : 1);
+                if (cheb) arrs = (first ? 1 : 3) + 2;
+                else if (!delta) arrs = (first ? 1 : 2) + ((flags & SW_LAST) ? 2 : 1);
                 else arrs = (first ? 1 : 2) + ((flags & SW_LAST) ? 2 : 2);
                 const int ncomp = c.ndim == 3 ? 3 : ((act & 1) ? 2 : 0) + ((act & 2) ? 1 : 0);
                 ProfScope ps(g, (flags & SW_LAST) ? MX_PROF_SWEEP_LAST : MX_PROF_SWEEP,
                              (double)g->ncell * sizeof(T) * arrs * ncomp);
                 if (c.ndim == 2 && g->variant == 1) e = launch_sweep2d<T>(k, act, kk, delta, flags, a, g->stream, &nwg);
-                else if (c.ndim == 2) e = launch_stream2d<T>(k, act, kk, delta, flags, a, g->stream, &nwg, 0);
+                else if (c.ndim == 2) e = launch_stream2d<T>(k, act, kk, form, flags, a, g->stream, &nwg, 0);
                 else e = launch_sweep3d<T>(k, kk, delta, flags, a, g->stream, &nwg);
             }
             if (e != hipSuccess) return fail(MX_EDEVICE, "sweep launch: %s", hipGetErrorString(e));
@@ -718,6 +797,7 @@ int mx_adjoint(mx_grid *g, int nsteps, const double *env, const int *sweeps, voi
         if (!Ebar[q] || !Bbar[q] || (dJ0 && !dJ0[q])) return fail(MX_EINVAL, "NULL component");
     for (int s = 0; s < 2 * nsteps; s++)
         if (sweeps[s] < 0) return fail(MX_EINVAL, "negative sweep count");
+    if (g->cfg.solver != MX_SOLVER_ALG1) return fail(MX_EINVAL, "the adjoint step follows Alg 1 only");
     HIPCHK(hipSetDevice(g->device));
     return g->cfg.dtype == MX_F64 ? adjoint_impl<double>(g, nsteps, env, sweeps, Ebar, Bbar, dJ0)
                                   : adjoint_impl<float>(g, nsteps, env, sweeps, Ebar, Bbar, dJ0);

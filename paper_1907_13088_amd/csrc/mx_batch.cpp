@@ -266,9 +266,9 @@ int mx_batch_workspace_size(const mx_config *cfgs, int ngrids, size_t *bytes)
         int rc = mx_validate(&c, nullptr);
         if (rc) return rc;
         if (c.ndim != 2 || c.blocks != MX_ALL || c.tol != 0.0 || c.lumped || c.sweeps < 1 || c.dtype != cfgs[0].dtype
-            || c.sweeps != cfgs[0].sweeps)
+            || c.sweeps != cfgs[0].sweeps || c.solver != MX_SOLVER_ALG1)
             return bfail(MX_EINVAL, "grid %d: a batch holds 2D TE+TM grids of one dtype, one fixed m >= 1, "
-                                    "no lumping", g);
+                                    "Alg 1, no lumping", g);
         tot += ARRAYS * up((size_t)cells(c) * (c.dtype == MX_F64 ? 8 : 4));
     }
     const size_t dsz = cfgs[0].dtype == MX_F64 ? sizeof(GridDesc<double>) : sizeof(GridDesc<float>);

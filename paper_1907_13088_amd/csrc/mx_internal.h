@@ -39,11 +39,21 @@ template <typename T>
 struct SweepArgs {
     const T *x_in[3];     // iterate (standard) or delta (delta form), with halo
     const T *rhs[3];      // dE' (standard form)
-    const T *s_in[3];     // running sum (delta form)
+    const T *s_in[3];     // running sum (delta form), increment (Chebyshev)
     T *x_out[3];
     T *s_out[3];
     T *E[3];
     double *partial;      // per-workgroup partial sums [nblocks][2] (TE, TM)
+    // Chebyshev form: per block (TE, TM) and sweep level of the pass, the
+    // factors of the previous increment and of the residual
+    T cheb[2][2][16];
+};
+
+// Iterate forms of the 2D streaming sweep pass (compile time)
+enum : int {
+    FM_STD = 0,     // x_(j+1) = b + A x_j (Alg 1)
+    FM_DELTA = 1,   // d_(j+1) = A d_j, s_(j+1) = s_j + d_(j+1)
+    FM_CHEB = 2,    // Chebyshev semi-iteration on (1 - A) x = b
 };
 
 template <typename T>
@@ -158,9 +168,9 @@ hipError_t launch_sweep2d(const Coef<T> &c, int blocks, int k, bool delta, int f
 // one pass of k sweeps over a block set (1 TE, 2 TM, 3 both) with the
 // row-streaming kernel; k in [1, stream2d_kmax(...)]
 template <typename T>
-hipError_t launch_stream2d(const Coef<T> &c, int block, int k, bool delta, int flags, const SweepArgs<T> &a,
+hipError_t launch_stream2d(const Coef<T> &c, int block, int k, int form, int flags, const SweepArgs<T> &a,
                            hipStream_t s, int *nwg, int slots);
-int stream2d_kmax(bool f64, int block, bool delta);
+int stream2d_kmax(bool f64, int block, int form);
 template <typename T>
 hipError_t launch_update(int64_t n, int comp_mask, T *const E[3], const T *const X[3], hipStream_t s);
 

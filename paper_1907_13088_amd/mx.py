@@ -21,6 +21,7 @@ MX_F32, MX_F64 = 0, 1
 MX_TE, MX_TM, MX_ALL = 1, 2, 3
 FORM_STANDARD, FORM_DELTA = 0, 1
 VARIANT_AUTO, VARIANT_TILE, VARIANT_STREAM, VARIANT_STREAM_BLOCK = 0, 1, 2, 3
+SOLVER_ALG1, SOLVER_CHEBYSHEV = 0, 1
 WARN_NOCONV_GUARANTEE = 1
 
 EXPORTS = ["mx_profile_enable", "mx_profile_read", "mx_last_error", "mx_config_default", "mx_validate", "mx_workspace_size", "mx_init",
@@ -40,7 +41,8 @@ class CConfig(C.Structure):
     _fields_ = [("ndim", C.c_int), ("n", C.c_int64 * 3), ("d", C.c_double * 3), ("dt", C.c_double),
                 ("dtype", C.c_int), ("blocks", C.c_int), ("sweeps", C.c_int), ("tol", C.c_double),
                 ("filter_passes", C.c_int), ("lumped", C.c_int), ("four_pi", C.c_double),
-                ("form", C.c_int), ("sweeps_per_pass", C.c_int), ("variant", C.c_int)]
+                ("form", C.c_int), ("sweeps_per_pass", C.c_int), ("variant", C.c_int),
+                ("solver", C.c_int)]
 
 
 class CProfile(C.Structure):
@@ -109,7 +111,8 @@ def _check(rc: int):
 def make_config(ndim: int, n: Sequence[int], dt: float, d: Sequence[float] = (1.0, 1.0, 1.0),
                 dtype: str = "f32", blocks: int = MX_ALL, sweeps: int = 20, tol: float = 0.0,
                 filter_passes: int = 0, lumped: bool = False, four_pi: float = 4.0 * math.pi,
-                form: int = FORM_STANDARD, sweeps_per_pass: int = 0, variant: int = 0) -> CConfig:
+                form: int = FORM_STANDARD, sweeps_per_pass: int = 0, variant: int = 0,
+                solver: int = 0) -> CConfig:
     """n and d are in axis order (x, y[, z])."""
     c = CConfig()
     lib().mx_config_default(C.byref(c))
@@ -130,6 +133,7 @@ def make_config(ndim: int, n: Sequence[int], dt: float, d: Sequence[float] = (1.
     c.form = int(form)
     c.sweeps_per_pass = int(sweeps_per_pass)
     c.variant = int(variant)
+    c.solver = int(solver)
     return c
 
 

@@ -26,18 +26,19 @@ def to_np(ts):
 
 
 def gpu_config(w, dtype=None, spp=0, form=mx.FORM_STANDARD, sweeps=None, tol=None, blocks=None,
-               lumped=False, variant=0):
+               lumped=False, variant=0, solver=0):
     n = w.shape[::-1]
     return mx.make_config(w.ndim, n, w.dt, w.d, dtype or w.dtype, blocks if blocks is not None else w.blocks,
                           w.sweeps if sweeps is None else sweeps, w.tol if tol is None else tol,
-                          w.filter_passes, lumped=lumped, form=form, sweeps_per_pass=spp, variant=variant)
+                          w.filter_passes, lumped=lumped, form=form, sweeps_per_pass=spp, variant=variant,
+                          solver=solver)
 
 
 def run_gpu(w, nsteps, dtype=None, spp=0, form=mx.FORM_STANDARD, replay=None, sweeps=None, tol=None,
-            blocks=None, lumped=False, E=None, B=None, variant=0):
+            blocks=None, lumped=False, E=None, B=None, variant=0, solver=0):
     import torch
     dt_ = dtype or w.dtype
-    cfg = gpu_config(w, dt_, spp, form, sweeps, tol, blocks, lumped, variant)
+    cfg = gpu_config(w, dt_, spp, form, sweeps, tol, blocks, lumped, variant, solver)
     g = mx.Grid(cfg)
     Et = torch_fields(w.E if E is None else E, dt_)
     Bt = torch_fields(w.B if B is None else B, dt_)
@@ -53,15 +54,16 @@ def run_gpu(w, nsteps, dtype=None, spp=0, form=mx.FORM_STANDARD, replay=None, sw
     return out
 
 
-def oracle_config(w, sweeps=None, tol=None, check_every=1, blocks=None, lumped=False):
+def oracle_config(w, sweeps=None, tol=None, check_every=1, blocks=None, lumped=False, solver=0):
     return ref.Config(ndim=w.ndim, shape=w.shape, dt=w.dt, d=w.d,
                       blocks=w.blocks if blocks is None else blocks,
                       sweeps=w.sweeps if sweeps is None else sweeps, tol=w.tol if tol is None else tol,
-                      check_every=check_every, filter_passes=w.filter_passes, lumped=lumped)
+                      check_every=check_every, filter_passes=w.filter_passes, lumped=lumped, solver=solver)
 
 
-def run_oracle(w, nsteps, sweeps=None, tol=None, check_every=1, replay=None, blocks=None, lumped=False):
-    cfg = oracle_config(w, sweeps, tol, check_every, blocks, lumped)
+def run_oracle(w, nsteps, sweeps=None, tol=None, check_every=1, replay=None, blocks=None, lumped=False,
+               solver=0):
+    cfg = oracle_config(w, sweeps, tol, check_every, blocks, lumped, solver)
     E = [a.copy() for a in w.E]
     B = [a.copy() for a in w.B]
     t0 = time.time()

@@ -27,9 +27,25 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
-def test_header_and_binding_struct_sizes_agree():
-    # mx_config: int, 3 int64, 3 double, double, 4 ints... sizes must match the C layout
-    assert C.sizeof(mx.CConfig) == 8 + 24 + 24 + 8 + 4 * 3 + 4 + 8 + 4 + 4 + 8 + 4 + 4 or C.sizeof(mx.CConfig) > 0
+def test_header_and_binding_struct_sizes_agree(tmp_path):
+    """The ctypes mirrors of mx_config, mx_step_stats and mx_profile have the
+    size and field offsets a C compiler gives the header's structs."""
+    import subprocess
+    structs = {"mx_config": mx.CConfig, "mx_step_stats": mx.CStats, "mx_profile": mx.CProfile}
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "mx.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        src.append(f'printf("%zu", sizeof({name}));')
+        for f, _ in cls._fields_:
+            src.append(f'printf(" %zu", offsetof({name}, {f}));')
+        src.append('printf("\\n");')
+    src.append("return 0; }")
+    (tmp_path / "probe.c").write_text("\n".join(src))
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.check_call(["gcc", "-I", inc, "-o", str(tmp_path / "probe"), str(tmp_path / "probe.c")])
+    out = subprocess.check_output([str(tmp_path / "probe")], text=True).split("\n")
+    for line, (name, cls) in zip(out, structs.items()):
+        want = [C.sizeof(cls)] + [getattr(cls, f).offset for f, _ in cls._fields_]
+        assert [int(v) for v in line.split()] == want, name
     c = mx.make_config(2, (16, 16), 0.3)
     assert mx.validate(c) == 0
 
@@ -54,6 +70,11 @@ def _cfg(**kw):
     (dict(sweeps_per_pass=17), mx.MX_EINVAL),
     (dict(sweeps_per_pass=9, variant=1), mx.MX_EINVAL),
     (dict(form=7), mx.MX_EINVAL),
+    (dict(solver=2), mx.MX_EINVAL),
+    (dict(solver=1, variant=1), mx.MX_EINVAL),
+    (dict(solver=1, form=1), mx.MX_EINVAL),
+    (dict(solver=1, lumped=True), mx.MX_EINVAL),
+    (dict(ndim=3, n=(8, 8, 8), dt=0.5 / math.sqrt(3), solver=1), mx.MX_EINVAL),
     (dict(ndim=3, n=(8, 8, 8), dt=0.5 / math.sqrt(3), blocks=1), mx.MX_EINVAL),
     (dict(ndim=3, n=(8, 8, 8), dt=0.5 / math.sqrt(3), sweeps_per_pass=3), mx.MX_EINVAL),
     (dict(ndim=3, n=(8, 8, 8), dt=0.5 / math.sqrt(3), dtype="f64", sweeps_per_pass=2), mx.MX_EINVAL),
