@@ -33,6 +33,8 @@ HBM_PEAK_GBS = 8000.0
 VALU_FP32_PEAK_TFLOPS = 78.6
 HERE = os.path.dirname(os.path.abspath(__file__))
 PROFILE_SUMMARY = os.path.join(HERE, "profiles", "sweep_pass_2d_4096sq_f32.md")
+# per-launch timing events are recorded on one step in PSTRIDE of the timed region
+PSTRIDE = 10
 
 
 def log(msg):
@@ -56,9 +58,10 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run 4 plain device copies of this many bytes (counter calibration)")
     ap.add_argument("--workload", default="modes2d",
-                    choices=["modes2d", "planewave_te", "planewave_3d", "batch", "adjoint"],
+                    choices=["modes2d", "planewave_te", "planewave_3d", "batch", "adjoint", "chebyshev"],
                     help="modes2d (default): the 4096^2 line above; the others time the 128^2 TE "
-                         "tolerance solve, the 512^3 3D solve, the 64-grid batch and the adjoint")
+                         "tolerance solve, the 512^3 3D solve, the 64-grid batch, the adjoint and the "
+                         "Chebyshev solve against Alg 1")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -119,17 +122,25 @@ def main():
         g, E, B, J = make(dtype)
         g.step(W, env[:W])
         torch.cuda.synchronize()
-        # per-launch HIP events on the library stream over the timed steps
+        # per-launch HIP events on the library stream, on every PSTRIDE-th
+        # step of the timed region (the event records themselves cost about
+        # 3 us per launch, so recording all of them would slow the run)
         g.profile_enable(True)
+        g.profile_enable(False)
         s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         wall0 = time.perf_counter()
         s0.record()
-        g.step(K, env[W:W + K])
+        for c0 in range(0, K, PSTRIDE):
+            g.profile_resume()
+            g.step(1, env[W + c0:W + c0 + 1])
+            g.profile_enable(False)
+            rest = min(PSTRIDE, K - c0) - 1
+            if rest > 0:
+                g.step(rest, env[W + c0 + 1:W + c0 + 1 + rest])
         s1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - wall0
         prof = g.profile_read()
-        g.profile_enable(False)
         ms = s0.elapsed_time(s1)
         log(f"{dtype}: {K} steps in {ms:.1f} ms (wall {wall * 1e3:.1f} ms), "
             f"sweeps per pass {g.block_sweeps_per_pass}")
@@ -180,6 +191,7 @@ def main():
                 "kernel": f"k2_stream<float,3,K> row-streaming sweep passes storing their iterate "
                           f"(K = {'+'.join(map(str, store))}; final pass K = {depths[-1]} adds into E)",
                 "bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_s * 1e6, 2), "launches": nl,
+                "timed_launches": f"HIP events on every launch of one step in {PSTRIDE} of the timed region",
                 "valu_tflops": round(flops_per_launch / avg_s / 1e12, 2) if avg_s > 0 else None,
                 "valu_peak_tflops": VALU_FP32_PEAK_TFLOPS,
                 "step_hbm_GBps": round(sum(v["bytes"] for v in prof.values()) / (total_ms / 1e3) / 1e9, 1)}
@@ -389,8 +401,93 @@ def bench_adjoint(steps, warm):
                           "transposed steps, source projection) over the same steps"})
 
 
+def _cheb_sweeps_matching_alg1(dt, d, m):
+    """Fewest Chebyshev sweeps whose worst-case error factor 1/T_k(theta/delta)
+    is at most Alg 1's rho^(m+1), for the TE and the TM block of a 2D grid
+    (the spectrum of A on a block is [0, rho]: TE 2/3, TM the largest corner
+    of its bilinear symbol)."""
+    import math
+    rx, ry = dt * dt / (d[0] * d[0]), dt * dt / (d[1] * d[1])
+    rhos = (2 / 3, max(2 / 3 * (1 - rx), 2 / 3 * (1 - ry), 8 / 9 - 2 / 9 * (rx + ry)))
+    need, bounds = 1, []
+    for rho in rhos:
+        x = (1 - rho / 2) / (rho / 2)
+        k = 1
+        while 1 / math.cosh(k * math.acosh(x)) > rho ** (m + 1):
+            k += 1
+        need = max(need, k)
+        bounds.append(rho ** (m + 1))
+    return need, rhos, bounds
+
+
+def bench_chebyshev(steps, warm):
+    """The Chebyshev solve against Alg 1: the 4096^2 FP32 TE+TM workload with
+    a sweep count of equal worst-case solve error per block, and the 128^2
+    FP64 TE plane wave to 1e-12."""
+    import math
+    import torch
+    from paper_1907_13088_amd import inputs as I
+    from paper_1907_13088_amd import mx
+    steps = steps or 200
+    warm = 5 if warm is None else warm
+    out = {}
+    # (a) 4096^2 FP32, fixed counts
+    n = 4096
+    w = I.modes_2d((n, n), steps=steps + warm, dtype="f32")
+    env = [float(x) for x in w.env]
+    kc, rhos, bounds = _cheb_sweeps_matching_alg1(w.dt, (1.0, 1.0), w.sweeps)
+    res = {}
+    for name, solver, m in (("alg1", mx.SOLVER_ALG1, w.sweeps), ("chebyshev", mx.SOLVER_CHEBYSHEV, kc)):
+        cfg = mx.make_config(2, (n, n), w.dt, (1.0, 1.0), "f32", mx.MX_ALL, m, 0.0, w.filter_passes, solver=solver)
+        g = mx.Grid(cfg)
+        E = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in w.E]
+        B = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in w.B]
+        J = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in w.J0]
+        g.bind(E, B)
+        g.set_current(J)
+        g.step(warm, env[:warm])
+        torch.cuda.synchronize()
+        s0, s1 = _events()
+        s0.record()
+        g.step(steps, env[warm:warm + steps])
+        s1.record()
+        torch.cuda.synchronize()
+        ms = s0.elapsed_time(s1)
+        res[name] = {"sweeps": m, "sweeps_per_pass": list(g.block_sweeps_per_pass),
+                     "Gcell_steps_per_s": round(n * n * steps / (ms / 1e3) / 1e9, 3),
+                     "ms_per_step": round(ms / steps, 4)}
+        g.close()
+        del E, B, J
+    res["solve_error_factor_bound"] = {"alg1_rho^(m+1)": [float(f"{b:.3g}") for b in bounds],
+                                       "chebyshev_1/T_k": [float(f"{1 / math.cosh(kc * math.acosh((1 - r / 2) / (r / 2))):.3g}")
+                                                           for r in rhos]}
+    out["4096sq_f32_equal_worst_case_error"] = res
+    # (b) 128^2 FP64 TE to 1e-12
+    wt = I.planewave_te_2d(steps=steps + warm)
+    res = {}
+    for name, solver in (("alg1", mx.SOLVER_ALG1), ("chebyshev", mx.SOLVER_CHEBYSHEV)):
+        cfg = mx.make_config(2, wt.shape[::-1], wt.dt, wt.d, "f64", wt.blocks, wt.sweeps, wt.tol, 0, solver=solver)
+        g = mx.Grid(cfg)
+        E = [torch.tensor(a, device="cuda") for a in wt.E]
+        B = [torch.tensor(a, device="cuda") for a in wt.B]
+        g.bind(E, B)
+        g.step(warm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = g.step(steps, stats=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[name] = {"mean_sweeps": round(sum(s.sweeps[0] for s in st) / steps, 2),
+                     "us_per_step": round(dt / steps * 1e6, 1), "sweeps_per_pass": g.sweeps_per_pass}
+        g.close()
+    out["128sq_te_f64_tol1e-12"] = res
+    a = out["4096sq_f32_equal_worst_case_error"]
+    return _line("Chebyshev vs Alg 1 solve, 4096^2 FP32 at equal worst-case solve error", 
+                 a["chebyshev"]["Gcell_steps_per_s"], "Gcell-steps/s", {"steps": steps, "results": out})
+
+
 OTHER_WORKLOADS = {"planewave_te": bench_planewave_te, "planewave_3d": bench_planewave_3d,
-                   "batch": bench_batch, "adjoint": bench_adjoint}
+                   "batch": bench_batch, "adjoint": bench_adjoint, "chebyshev": bench_chebyshev}
 
 
 if __name__ == "__main__":

@@ -181,8 +181,11 @@ int mx_destroy(mx_grid *g);
  * Per-kernel timing.  While enabled, every launch of mx_step / mx_adjoint is
  * bracketed by HIP events recorded on the grid's stream, and its algorithmic
  * HBM traffic (each array a kernel must read or write, counted once per
- * touched cell) is added to its category.  mx_profile_enable resets the
- * counters; mx_profile_read waits for the stream and sums the event times.
+ * touched cell) is added to its category.  mx_profile_enable(g, 1) resets
+ * the counters and starts recording, (g, 0) pauses (the counters are kept),
+ * (g, 2) resumes without a reset, so that a caller can sample some steps of
+ * a longer run; mx_profile_read waits for the stream and sums the event
+ * times recorded since the last reset.
  * ------------------------------------------------------------------------ */
 #define MX_PROF_FRONT      0  /* filter + Faraday + auxiliary increment */
 #define MX_PROF_SWEEP      1  /* mass-matrix sweep passes that store the iterate */

@@ -439,10 +439,13 @@ int mx_destroy(mx_grid *g)
 int mx_profile_enable(mx_grid *g, int on)
 {
     if (!g) return fail(MX_EINVAL, "grid is NULL");
+    if (on < 0 || on > 2) return fail(MX_EINVAL, "on must be 0 (pause), 1 (reset and record) or 2 (resume)");
     g->prof = on != 0;
-    g->ev_used = 0;
-    g->ev_cat.clear();
-    for (int i = 0; i < MX_PROF_NCAT; i++) { g->launches[i] = 0; g->bytes[i] = 0.0; }
+    if (on == 1) {
+        g->ev_used = 0;
+        g->ev_cat.clear();
+        for (int i = 0; i < MX_PROF_NCAT; i++) { g->launches[i] = 0; g->bytes[i] = 0.0; }
+    }
     return MX_OK;
 }
 

@@ -256,7 +256,12 @@ class Grid:
                                         C.c_void_p(shapes.data_ptr()), _ptrs(G), C.c_void_p(grad.data_ptr())))
 
     def profile_enable(self, on: bool = True):
+        """True: reset the per-kernel timers and record; False: pause."""
         _check(lib().mx_profile_enable(self.h, int(bool(on))))
+
+    def profile_resume(self):
+        """Record again without resetting (sample some steps of a run)."""
+        _check(lib().mx_profile_enable(self.h, 2))
 
     def profile_read(self) -> dict:
         p = CProfile()
