@@ -10,7 +10,8 @@
  *      paper filters the current (Sec. 4.2, Sec. 5) without naming a stencil
  *   3. dE' = c dt curl(Lambda B^{n+1/2}) - 4 pi dt Jf  (eqs ampere_aux_x..z)
  *   4. (1 - A) dE = dE' by the fixed-point sweeps of Alg 1,
- *      A from eqs matrixA_1st..matrixA_last (2D: matrixA_*_2d)
+ *      A from eqs matrixA_1st..matrixA_last (2D: matrixA_*_2d); in 2D
+ *      optionally by the Chebyshev semi-iteration (MX_SOLVER_CHEBYSHEV)
  *   5. E^{n+1} = E^n + dE
  * with c = 1, periodic boundaries in every axis.
  *
@@ -115,7 +116,9 @@ typedef struct mx_config {
 
 typedef struct mx_step_stats {
     int sweeps[2];        /* sweeps taken per block (2D: TE, TM; 3D: [0]) */
-    double resid[2];      /* last step norm ||dE_(j+1) - dE_(j)||_2 (tol mode) */
+    double resid[2];      /* last step norm ||dE_(j+1) - dE_(j)||_2 (tol mode;
+                             the Chebyshev solve: the residual ||dE' + A x - x||_2
+                             of its last sweep's input, the same quantity) */
     double rhs[2];        /* ||dE'||_2 (tol mode) */
     int nonconverged[2];  /* tol mode: m_max reached above tolerance */
 } mx_step_stats;
@@ -126,7 +129,7 @@ typedef struct mx_grid mx_grid;
 const char *mx_last_error(void);
 
 /* Fill *cfg with defaults: 2D, unit cells, FP32, MX_ALL, m = 20, tol = 0,
-   no filter, 4 pi, standard form.  n and dt must still be set. */
+   no filter, 4 pi, standard form, Alg 1.  n and dt must still be set. */
 int mx_config_default(mx_config *cfg);
 
 /* Host-only validation (no device call): ranges, enums and the CFL bound
