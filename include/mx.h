@@ -105,7 +105,8 @@ typedef struct mx_config {
                              delta form 6, 3; per block TE 10 (FP32), 5 (FP64),
                              delta 9, 4; TM 16 (FP32), 8 (FP64).  LDS tile: <= 8.
                              3D: 1 (library choice) or 2 in FP32, 1 in FP64. */
-    int variant;          /* 2D sweep kernel: 0 library choice (FP32: 2, FP64: 3),
+    int variant;          /* 2D sweep kernel: 0 library choice (FP32: 2, FP64 and
+                             the Chebyshev solve: 3),
                              1 LDS tile (both blocks per pass), 2 row streaming
                              (both blocks per pass), 3 row streaming (each block
                              on its own) */
