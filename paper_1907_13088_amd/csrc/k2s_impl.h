@@ -17,6 +17,8 @@
 // (slot 0 of a level's carried window holds the carried value of the row the
 // level produced last; the next level reads it before the producer shifts).
 // Delta form:    d_l = A d_(l-1), s_l = s_(l-1) + d_l, s carried along.
+// Chebyshev form: r = b + A x_(l-1) - x_(l-1), d_l = f_l d_(l-1) + g_l r,
+// x_l = x_(l-1) + d_l, with b and d carried along (f, g per sweep and block).
 #include <algorithm>
 #include <type_traits>
 
@@ -149,8 +151,6 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
         xb[q] = first ? a.rhs[q] : a.x_in[q];
         cb[q] = (DELTA && !first) ? a.s_in[q] : a.rhs[q];
     }
-    // Chebyshev form: the increment of the input iterate (zero before the
-    // first sweep; s_in is then any valid buffer and its values are unused)
     // byte offset of the next level-0 row to load, advanced with a wrap
     // (a uniform scalar), plus the thread's column
     const unsigned rowb = (unsigned)nx * (unsigned)sizeof(T);
@@ -165,6 +165,8 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
             if ((q < 2 && !TE) || (q == 2 && !TM)) continue;
             x[q] = ld_off(xb[q], o);
             cc[q] = ld_off(cb[q], o);
+            // Chebyshev form: the increment that produced the input iterate
+            // (none before the first sweep: the values read are then unused)
             if (CHEB) dd[q] = ld_off(a.s_in[q], o);
         }
         lo += rowb;
