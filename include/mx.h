@@ -75,8 +75,9 @@ extern "C" {
    (Sec. 2.2.1).  It counts sweeps like Alg 1 (one application of A each)
    and its tolerance test uses the same residual ||dE' + A x - x||_2, but
    its iterates differ: it reaches a given residual in far fewer sweeps.
-   2D row streaming only (variants 0, 2, 3), standard form, not lumped; no
-   batch or adjoint. */
+   2D row streaming only (variants 0, 2, 3), standard form, not lumped; not
+   in a batch.  Its result after m sweeps is a polynomial in A applied to
+   dE', so mx_adjoint transposes it with the same kernels. */
 #define MX_SOLVER_ALG1      0
 #define MX_SOLVER_CHEBYSHEV 1
 
@@ -210,8 +211,8 @@ int mx_profile_read(mx_grid *g, mx_profile *out);
  * Transposed (adjoint) step.  The step is linear in (E, B, J0):
  *   B+ = B - dt K E,   E+ = E + P (dt K^T Lambda B+ - 4 pi dt env F J0),
  * K the E->B curl of eqs faraday_*, K^T the B->E curl of eqs ampere_aux_*,
- * Lambda = diag(alpha_x, alpha_y, alpha_z), P = sum_{j<=m} A^j (Alg 1) and
- * F the filter.  A is symmetric (Appendix C), as are Lambda and F, so the
+ * Lambda = diag(alpha_x, alpha_y, alpha_z), P = sum_{j<=m} A^j (Alg 1; the
+ * Chebyshev solve's P is its polynomial in A after m sweeps) and F the filter.  A is symmetric (Appendix C), as are Lambda and F, so the
  * transposed step is
  *   v = P Ebar;  Bbar += dt Lambda K v;  Ebar -= dt K^T Bbar;
  *   dJ0 += env (-4 pi dt) F v.

@@ -803,7 +803,6 @@ int mx_adjoint(mx_grid *g, int nsteps, const double *env, const int *sweeps, voi
         if (!Ebar[q] || !Bbar[q] || (dJ0 && !dJ0[q])) return fail(MX_EINVAL, "NULL component");
     for (int s = 0; s < 2 * nsteps; s++)
         if (sweeps[s] < 0) return fail(MX_EINVAL, "negative sweep count");
-    if (g->cfg.solver != MX_SOLVER_ALG1) return fail(MX_EINVAL, "the adjoint step follows Alg 1 only");
     HIPCHK(hipSetDevice(g->device));
     return g->cfg.dtype == MX_F64 ? adjoint_impl<double>(g, nsteps, env, sweeps, Ebar, Bbar, dJ0)
                                   : adjoint_impl<float>(g, nsteps, env, sweeps, Ebar, Bbar, dJ0);

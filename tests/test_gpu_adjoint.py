@@ -17,15 +17,17 @@ from gpu_helpers import log, torch_fields, to_np
 pytestmark = pytest.mark.gpu
 
 
-def _grid(ndim, shape, dt, dtype, sweeps, p, blocks=3):
+def _grid(ndim, shape, dt, dtype, sweeps, p, blocks=3, solver=0):
     import torch
     n = shape[::-1]
-    cfg = mx.make_config(ndim, n, dt, (1.0, 1.0, 1.0)[:ndim], dtype, blocks, sweeps, 0.0, p)
+    cfg = mx.make_config(ndim, n, dt, (1.0, 1.0, 1.0)[:ndim], dtype, blocks, sweeps, 0.0, p, solver=solver)
     return mx.Grid(cfg)
 
 
-@pytest.mark.parametrize("ndim,shape", [(2, (80, 96)), (3, (12, 16, 20))])
-def test_adjoint_matches_oracle(ndim, shape):
+@pytest.mark.parametrize("ndim,shape,solver", [(2, (80, 96), 0), (3, (12, 16, 20), 0), (2, (80, 96), 1)])
+def test_adjoint_matches_oracle(ndim, shape, solver):
+    """The transposed step (with the Chebyshev solve too: its result is a
+    polynomial in the symmetric A applied to dE', so v = q_m(A) E-bar)."""
     rng = np.random.default_rng(60 + ndim)
     dt = 0.55 / math.sqrt(ndim)
     m, p, nsteps = 4, (2 if ndim == 2 else 1), 4
@@ -33,11 +35,11 @@ def test_adjoint_matches_oracle(ndim, shape):
     counts = [(m, m)] * nsteps
     Eb = [rng.normal(size=shape) for _ in range(3)]
     Bb = [rng.normal(size=shape) for _ in range(3)]
-    cfg = ref.Config(ndim=ndim, shape=shape, dt=dt, sweeps=m, filter_passes=p)
+    cfg = ref.Config(ndim=ndim, shape=shape, dt=dt, sweeps=m, filter_passes=p, solver=solver)
     Eo, Bo, Jo = [a.copy() for a in Eb], [a.copy() for a in Bb], [np.zeros(shape) for _ in range(3)]
     for n in reversed(range(nsteps)):
         ref.adjoint_step(cfg, Eo, Bo, Jo, envs[n], counts[n])
-    g = _grid(ndim, shape, dt, "f64", m, p)
+    g = _grid(ndim, shape, dt, "f64", m, p, solver=solver)
     Et, Bt = torch_fields(Eb, "f64"), torch_fields(Bb, "f64")
     Jt = torch_fields([np.zeros(shape)] * 3, "f64")
     g.adjoint(nsteps, envs, counts, Et, Bt, Jt)
@@ -45,11 +47,12 @@ def test_adjoint_matches_oracle(ndim, shape):
     want = Eo + Bo + Jo
     scale = max(np.abs(x).max() for x in want)
     err = max(np.abs(a - b).max() for a, b in zip(got, want)) / scale
-    log(f"adjoint {ndim}D vs oracle: {err:.2e}")
+    log(f"adjoint {ndim}D solver {solver} vs oracle: {err:.2e}")
     assert err < 1e-12
 
 
-def test_adjoint_dot_product_on_gpu():
+@pytest.mark.parametrize("solver", [0, 1])
+def test_adjoint_dot_product_on_gpu(solver):
     """<T x, y> = <x, T^T y> with T the GPU's multi-step map (E, B, J0) -> (E, B)."""
     import torch
     rng = np.random.default_rng(70)
@@ -59,7 +62,7 @@ def test_adjoint_dot_product_on_gpu():
     envs = [math.sin(0.3 * (n + 0.5) * dt) for n in range(nsteps)]
     x = [rng.normal(size=shape) for _ in range(9)]
     y = [rng.normal(size=shape) for _ in range(6)]
-    g = _grid(2, shape, dt, "f64", m, p)
+    g = _grid(2, shape, dt, "f64", m, p, solver=solver)
     E, B, J = torch_fields(x[:3], "f64"), torch_fields(x[3:6], "f64"), torch_fields(x[6:], "f64")
     g.bind(E, B)
     g.set_current(J)

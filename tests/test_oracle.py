@@ -557,13 +557,14 @@ def _fwd(cfg, E, B, J0, envs, counts):
     return E, B
 
 
-@pytest.mark.parametrize("ndim", [2, 3])
-def test_adjoint_dot_product(ndim):
-    """<T x, y> = <x, T^T y> for the whole multi-step map (E, B, J0) -> (E, B)."""
+@pytest.mark.parametrize("ndim,solver", [(2, 0), (3, 0), (2, 1)])
+def test_adjoint_dot_product(ndim, solver):
+    """<T x, y> = <x, T^T y> for the whole multi-step map (E, B, J0) -> (E, B)
+    (with the Chebyshev solve too: a polynomial in the symmetric A)."""
     rng = np.random.default_rng(40 + ndim)
     shape = (7, 6) if ndim == 2 else (4, 5, 3)
     dt = 0.55 / math.sqrt(ndim)
-    cfg = ref.Config(ndim=ndim, shape=shape, dt=dt, sweeps=5, filter_passes=2)
+    cfg = ref.Config(ndim=ndim, shape=shape, dt=dt, sweeps=5, filter_passes=2, solver=solver)
     envs = [0.3, -0.8, 1.1]
     counts = [(5, 5)] * 3
     E = [rng.normal(size=shape) for _ in range(3)]
