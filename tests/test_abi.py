@@ -115,6 +115,9 @@ def test_workspace_size_and_null_workspace():
     assert rc == mx.MX_EWORKSPACE and not h.value
     rc = mx.lib().mx_init(C.byref(c), None, C.c_void_p(4096), 16, C.byref(h))
     assert rc == mx.MX_EWORKSPACE
+    # the Chebyshev solve double-buffers its increments: three arrays more
+    cc = _cfg(dtype="f64", solver=mx.SOLVER_CHEBYSHEV)
+    assert mx.workspace_size(cc) - nbytes == 3 * 32 * 32 * 8
 
 
 def test_step_rejects_null_grid():

@@ -112,3 +112,19 @@ def test_cheb_rejections():
         mx.Grid(gpu_config(w, variant=mx.VARIANT_TILE, solver=CHEB))
     with pytest.raises(mx.MxError):
         mx.Grid(gpu_config(w, lumped=True, solver=CHEB))
+
+
+def test_cheb_fp32_tolerance_1e6():
+    """FP32 Chebyshev solve to tol 1e-6 (above the FP32 rounding floor of
+    the residual b + A x - x): every step converges, and the fields agree
+    with the FP64 oracle run on the GPU's own counts within 1e-5."""
+    w = I.modes_2d((136, 120), nmodes=32, npulses=4, filter_passes=2, m=200, steps=12, seed=2104, dtype="f32")
+    w.tol = 1e-6
+    nsteps = 10
+    Eg, Bg, stg, _ = run_gpu(w, nsteps, solver=CHEB)
+    assert all(tuple(s.nonconverged) == (0, 0) for s in stg)
+    assert all(0 < s.sweeps[0] < 200 and 0 < s.sweeps[1] < 200 for s in stg)
+    Eo, Bo, _ = run_oracle(w, nsteps, replay=[s.sweeps for s in stg], solver=CHEB)
+    e = rel_err(Eg + Bg, Eo + Bo)
+    log(f"chebyshev fp32 tol 1e-6: sweeps {[tuple(s.sweeps) for s in stg][:3]}, errors {max(e):.2e}")
+    assert max(e) < 1e-5
