@@ -155,7 +155,7 @@ constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 // All nsteps steps of all grids in one launch; npass passes per step, the
 // first nlow of Q - 1 sweeps, the others of Q.
 template <typename T, int Q>
-__global__ __launch_bounds__(RX, 2) void kb_persistent(const GridDesc<T> *d, int ng, const int *items_f,
+__global__ __launch_bounds__(RX, sizeof(T) == 4 ? 2 : 1) void kb_persistent(const GridDesc<T> *d, int ng, const int *items_f,
                                                     const int *items_s, int Lf, int Ls, int nsteps, int npass,
                                                     int nlow, int bin0, unsigned *bar, int *err)
 {
