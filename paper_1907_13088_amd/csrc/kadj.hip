@@ -230,6 +230,19 @@ hipError_t launch_sources(int nx, int ny, int nsrc, int W, const int64_t *origin
     return hipGetLastError();
 }
 
+// acc[q] = 0 (zero != 0) or acc[q] += a x[q], for the components in mask
+template <typename T>
+hipError_t launch_axpy3(int64_t n, int mask, bool zero, T a, const T *const x[3], T *const acc[3], hipStream_t s)
+{
+    const unsigned nb = (unsigned)((n + NT - 1) / NT);
+    for (int q = 0; q < 3; q++) {
+        if (!(mask & (1 << q))) continue;
+        if (zero) hipLaunchKernelGGL((k_fill<T>), dim3(nb), dim3(NT), 0, s, n, acc[q]);
+        else hipLaunchKernelGGL((k_axpy<T>), dim3(nb), dim3(NT), 0, s, n, a, x[q], acc[q]);
+    }
+    return hipGetLastError();
+}
+
 #define INST(T)                                                                                       \
     template hipError_t launch_adj_curlB<T>(const Coef<T> &, int, int, const T *const[3], T *const[3], \
                                             hipStream_t);                                             \
@@ -238,7 +251,8 @@ hipError_t launch_sources(int nx, int ny, int nsrc, int W, const int64_t *origin
     template hipError_t launch_adj_source<T>(const Coef<T> &, int, int, const T *const[3], T *const[3], \
                                              T *const[3], T, T *const[3], hipStream_t);               \
     template hipError_t launch_sources<T>(int, int, int, int, const int64_t *, const T *, const T *,  \
-                                          T *const[3], T *const[3], T *, bool, hipStream_t);
+                                          T *const[3], T *const[3], T *, bool, hipStream_t);           \
+    template hipError_t launch_axpy3<T>(int64_t, int, bool, T, const T *const[3], T *const[3], hipStream_t);
 INST(float)
 INST(double)
 #undef INST

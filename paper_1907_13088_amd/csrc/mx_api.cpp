@@ -753,6 +753,20 @@ int adjoint_impl(mx_grid *g, int nsteps, const double *env, const int *sweeps, v
 {
     const mx_config &c = g->cfg;
     const Coef<T> &k = coef<T>(g);
+    const double arr = (double)g->ncell * sizeof(T);
+    // The current gradient sum_n env_n (-4 pi dt) F v_n is F applied once to
+    // sum_n env_n (-4 pi dt) v_n (F is linear): the steps accumulate the
+    // unfiltered sum in a buffer the adjoint does not otherwise use (the B
+    // workspace in 2D, the filtered-current buffer in 3D), filtered at the end
+    T *const *acc = (T *const *)(c.ndim == 2 ? g->Bws : g->Jf);
+    const int cmask = c.ndim == 3 ? 7 : ((c.blocks & 1) ? 3 : 0) | ((c.blocks & 2) ? 4 : 0);
+    bool any_src = false;
+    if (dJ0) {
+        // all three components start at zero: a block the grid does not step
+        // keeps a zero current gradient
+        ProfScope ps(g, MX_PROF_ADJOINT, arr * 3);
+        HIPCHK(launch_axpy3<T>(g->ncell, 7, true, T(0), acc, acc, g->stream));
+    }
     for (int s = nsteps - 1; s >= 0; s--) {
         int target[2] = {sweeps[2 * s], sweeps[2 * s + 1]};
         const T *v[3];
@@ -760,22 +774,26 @@ int adjoint_impl(mx_grid *g, int nsteps, const double *env, const int *sweeps, v
         // v = P Ebar
         int rc = run_sweeps<T>(g, Ebar, target, false, nullptr, nullptr, e_done, v, nullptr);
         if (rc) return rc;
-        const double arr = (double)g->ncell * sizeof(T);
         {
             ProfScope ps(g, MX_PROF_ADJOINT, arr * 9);
             HIPCHK(launch_adj_curlB<T>(k, c.ndim, c.blocks, v, (T *const *)Bbar, g->stream));
         }
-        if (dJ0) {
-            const T scale = (T)(-(env ? env[s] : 0.0) * c.four_pi * c.dt);
-            // filter temporaries: dE' and the running-sum buffers are free here
-            ProfScope ps(g, MX_PROF_ADJOINT, arr * 3 * (2 * c.ndim * c.filter_passes + 3));
-            HIPCHK(launch_adj_source<T>(k, c.ndim, c.filter_passes, v, (T *const *)g->dEp, (T *const *)g->S,
-                                        scale, (T *const *)dJ0, g->stream));
+        const double sc = -(env ? env[s] : 0.0) * c.four_pi * c.dt;
+        if (dJ0 && sc != 0.0) {
+            ProfScope ps(g, MX_PROF_ADJOINT, arr * 3 * 3);
+            HIPCHK(launch_axpy3<T>(g->ncell, cmask, false, (T)sc, v, acc, g->stream));
+            any_src = true;
         }
         {
             ProfScope ps(g, MX_PROF_ADJOINT, arr * 9);
             HIPCHK(launch_adj_curlE<T>(k, c.ndim, c.blocks, (const T *const *)Bbar, (T *const *)Ebar, g->stream));
         }
+    }
+    if (any_src) {
+        // dJ0 += F acc; filter temporaries: dE' and the running-sum buffers
+        ProfScope ps(g, MX_PROF_ADJOINT, arr * 3 * (2 * c.ndim * c.filter_passes + 3));
+        HIPCHK(launch_adj_source<T>(k, c.ndim, c.filter_passes, (const T *const *)acc, (T *const *)g->dEp,
+                                    (T *const *)g->S, T(1), (T *const *)dJ0, g->stream));
     }
     return MX_OK;
 }

@@ -206,5 +206,7 @@ template <typename T>
 hipError_t launch_sources(int nx, int ny, int nsrc, int W, const int64_t *origins, const T *shapes,
                           const T *amps, T *const J0[3], T *const G[3], T *grad, bool project,
                           hipStream_t s);
+template <typename T>
+hipError_t launch_axpy3(int64_t n, int mask, bool zero, T a, const T *const x[3], T *const acc[3], hipStream_t s);
 
 }  // namespace mx
