@@ -18,8 +18,9 @@
  * Memory model.  The caller owns every byte of device memory: field
  * buffers are borrowed device pointers and the library's scratch lives in a
  * caller-provided workspace of mx_workspace_size() bytes.  The library never
- * allocates device memory.  All kernels run on the HIP stream given to
- * mx_init (NULL = the default stream).
+ * allocates device memory (mx_init takes 16 bytes of pinned host memory, to
+ * read the tolerance test's norms back).  All kernels run on the HIP stream
+ * given to mx_init (NULL = the default stream).
  *
  * Layout.  Each field component is one dense array in the grid dtype
  * (float or double), x fastest: index (k*ny + j)*nx + i, nz = 1 in 2D.
