@@ -11,14 +11,14 @@ template <typename T, int BLK, int P, bool HASJ>
 hipError_t front_j(const Coef<T> &c, const FrontArgs<T> &a, const T *const Bin[3], hipStream_t s, int *nwg)
 {
     constexpr int W = front_aligned() ? FRX - 32 : FRX - (P > 1 ? P : 1) - (P > 2 ? P : 2);
-    static int slots = -1;
-    if (slots < 0) {
+    static std::atomic<int> resident[MX_MAX_DEVICES];
+    const int slots = per_device(resident, [] {
         int o = 0, dev = 0, cu = 0;
         (void)hipGetDevice(&dev);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k2_front_stream<T, BLK, P, FRX, HASJ>, FRX, 0) != hipSuccess || o < 1) o = 1;
         if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu < 1) cu = 256;
-        slots = std::min(o, 4) * cu;
-    }
+        return std::min(o, 4) * cu;
+    });
     const int nsx = (c.nx + W - 1) / W;
     int nsy = std::max(1, slots / nsx);
     nsy = std::min(nsy, c.ny);

@@ -394,16 +394,15 @@ template <typename T, int BLK, int K, int FORM, int OM>
 hipError_t stream_om(const Coef<T> &c, int flags, const SweepArgs<T> &a, hipStream_t s, int *nwg, int slots)
 {
     constexpr int W = stream_width<SRX>(K);
-    static int occ = -1, ncu = -1;
-    if (occ < 0) {
-        int o = 0, dev = 0, cu = 0;
-        (void)hipGetDevice(&dev);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k2_stream<T, BLK, K, FORM, SRX, OM>, SRX, 0) != hipSuccess || o < 1) o = 1;
-        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu < 1) cu = 256;
-        ncu = cu;
-        occ = o;
-    }
-    if (slots <= 0) slots = occ * ncu;
+    static std::atomic<int> resident[MX_MAX_DEVICES];
+    if (slots <= 0)
+        slots = per_device(resident, [] {
+            int o = 0, dev = 0, cu = 0;
+            (void)hipGetDevice(&dev);
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k2_stream<T, BLK, K, FORM, SRX, OM>, SRX, 0) != hipSuccess || o < 1) o = 1;
+            if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu < 1) cu = 256;
+            return o * cu;
+        });
     const int nsx = (c.nx + W - 1) / W;
     // one resident round: choose the chunk count so that strips x chunks fill
     // the resident workgroup slots, then round the chunk length up

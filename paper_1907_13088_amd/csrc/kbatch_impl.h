@@ -236,15 +236,14 @@ hipError_t launch_sweep_impl(const GridDesc<T> *d, int ng, const int *items, int
 template <typename T, int Q>
 int occ_q()
 {
-    static int n = -1;
-    if (n < 0) {
+    static std::atomic<int> resident[MX_MAX_DEVICES];
+    return per_device(resident, [] {
         int o = 0, dev = 0, cu = 0;
         (void)hipGetDevice(&dev);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, kb_persistent<T, Q>, RX, 0) != hipSuccess) o = 0;
         if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cu = 0;
-        n = o * cu;
-    }
-    return n;
+        return o * cu;
+    });
 }
 
 template <typename T, int Q>

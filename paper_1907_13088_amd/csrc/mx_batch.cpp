@@ -209,7 +209,7 @@ int persistent_steps(mx_batch *b, int nsteps, int bin0)
     return MX_OK;
 }
 
-// Time two steps of each candidate plan (pass depth cap x chunk rows) on
+// Time four steps of each candidate plan (pass depth cap x chunk rows) on
 // scratch fields, for the grouped and for the persistent schedule.
 template <typename T>
 int autotune(mx_batch *b, bool grouped, bool persistent)
@@ -219,7 +219,7 @@ int autotune(mx_batch *b, bool grouped, bool persistent)
     BCHK(hipEventCreate(&e1));
     // FP32 passes fit two waves per SIMD up to 7 sweeps, FP64 up to 3
     const std::vector<int> ks = sizeof(T) == 4 ? std::vector<int>{4, 5, 6, 7} : std::vector<int>{2, 3, 4};
-    const int ls[] = {32, 64, 128};
+    const int ls[] = {48, 64, 96, 128, 192, 256};
     for (int sched = 0; sched < 2; sched++) {
         if ((sched == 0 && !grouped) || (sched == 1 && !persistent)) continue;
         float best = 1e30f;
@@ -234,7 +234,7 @@ int autotune(mx_batch *b, bool grouped, bool persistent)
                 rc = sched == 0 ? grouped_steps<T>(b, 1, 0) : persistent_steps<T>(b, 1, 0);   // warm
                 if (!rc) {
                     BCHK(hipEventRecord(e0, b->stream));
-                    rc = sched == 0 ? grouped_steps<T>(b, 2, 0) : persistent_steps<T>(b, 2, 0);
+                    rc = sched == 0 ? grouped_steps<T>(b, 4, 0) : persistent_steps<T>(b, 4, 0);
                     BCHK(hipEventRecord(e1, b->stream));
                 }
                 b->spp = keep[0]; b->Lf = keep[1]; b->Ls = keep[2];

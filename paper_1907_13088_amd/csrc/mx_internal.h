@@ -4,9 +4,28 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "../../include/mx.h"
 
 namespace mx {
+
+// A launch-shape figure of the current device (resident workgroups of a
+// kernel), computed on first use on each device and kept.  Host threads may
+// race on the first use: each then computes the same value.
+constexpr int MX_MAX_DEVICES = 64;
+template <typename F>
+inline int per_device(std::atomic<int> (&cache)[MX_MAX_DEVICES], F &&compute)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MX_MAX_DEVICES) return compute();
+    int v = cache[dev].load(std::memory_order_relaxed);
+    if (v == 0) {
+        v = compute() + 1;   // stored biased by one: zero means "not yet computed"
+        cache[dev].store(v, std::memory_order_relaxed);
+    }
+    return v - 1;
+}
 
 // Per-grid scalar coefficients, computed on the host in FP64 and rounded
 // once to the kernel type.  r_i = (c dt / d_i)^2, r_ij = (c dt)^2/(d_i d_j).
