@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -211,12 +212,23 @@ int persistent_steps(mx_batch *b, int nsteps, int bin0)
 
 // Time four steps of each candidate plan (pass depth cap x chunk rows) on
 // scratch fields, for the grouped and for the persistent schedule.
+// two timing events, destroyed on every return path
+struct EventPair {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~EventPair()
+    {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
 template <typename T>
 int autotune(mx_batch *b, bool grouped, bool persistent)
 {
-    hipEvent_t e0, e1;
-    BCHK(hipEventCreate(&e0));
-    BCHK(hipEventCreate(&e1));
+    EventPair ev;
+    BCHK(hipEventCreate(&ev.e0));
+    BCHK(hipEventCreate(&ev.e1));
+    const hipEvent_t e0 = ev.e0, e1 = ev.e1;
     // FP32 passes fit two waves per SIMD up to 7 sweeps, FP64 up to 3
     const std::vector<int> ks = sizeof(T) == 4 ? std::vector<int>{4, 5, 6, 7} : std::vector<int>{2, 3, 4};
     const int ls[] = {48, 64, 96, 128, 192, 256};
@@ -248,8 +260,6 @@ int autotune(mx_batch *b, bool grouped, bool persistent)
         if (sched == 0) { b->spp = bk; b->Lf = b->Ls = bl; }
         else { b->pk = bk; b->pLf = b->pLs = bl; }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
     return MX_OK;
 }
 
@@ -292,7 +302,9 @@ int mx_batch_init(const mx_config *cfgs, int ngrids, void *stream, void *workspa
     BCHK(hipPointerGetAttributes(&attr, workspace));
     if (attr.type != hipMemoryTypeDevice) return bfail(MX_EINVAL, "workspace is not device memory");
     BCHK(hipSetDevice(attr.device));
-    mx_batch *b = new mx_batch();
+    // owned here until the batch is complete: every early return frees it
+    std::unique_ptr<mx_batch> hold(new mx_batch());
+    mx_batch *b = hold.get();
     b->ng = ngrids;
     b->dtype = cfgs[0].dtype;
     b->m = cfgs[0].sweeps;
@@ -324,10 +336,10 @@ int mx_batch_init(const mx_config *cfgs, int ngrids, void *stream, void *workspa
     b->tuned = false;
     if (cfgs[0].sweeps_per_pass == 0) {
         rc = b->dtype == MX_F64 ? autotune<double>(b, true, true) : autotune<float>(b, true, true);
-        if (rc) { delete b; return rc; }
+        if (rc) return rc;
         b->tuned = true;
     }
-    *out = b;
+    *out = hold.release();
     return MX_OK;
 }
 
