@@ -361,7 +361,9 @@ def bench_batch(steps, warm):
         torch.cuda.synchronize()
         ms = s0.elapsed_time(s1)
         res["persistent" if persistent else "grouped"] = {"Gcell_steps_per_s": round(cells * steps / ms / 1e6, 3),
-                                                          "ms": round(ms, 1), "plan": b.plan()}
+                                                          "ms": round(ms, 1),
+                                                          "plan": {**b.schedule(persistent),
+                                                                   "persistent_blocks": b.plan()["persistent_blocks"]}}
         b.close()
     return _line("64 batched 2D grids, FP32, m = 20", res["persistent"]["Gcell_steps_per_s"], "Gcell-steps/s",
                  {"steps": steps, "cells": cells, "dtype": "f32", "schedules": res})

@@ -93,6 +93,7 @@ __device__ __forceinline__ void front_tile(const Coef<T> &c, const FrontArgs<T> 
     const int i = threadIdx.x;
     const int li = i + PADL;
     const int X0 = sx * W, Y0 = sy * L;
+    L = std::min(L, c.ny - Y0);   // a grid's last chunk may be short: run only its rows
     const int gxi = X0 - HL + i;
     const int gx = wrapi(gxi, nx);
     const bool outcol = i >= HL && i < HL + W && gxi < nx;

@@ -110,6 +110,7 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
     const int nx = c.nx, ny = c.ny;
     const int i = threadIdx.x;
     const int X0 = sx * W, Y0 = sy * L;
+    L = std::min(L, c.ny - Y0);   // a grid's last chunk may be short: run only its rows
     const int gxi = X0 - H + i;
     const int gx = wrapi(gxi, nx);
     const bool first = flags & SW_FIRST;

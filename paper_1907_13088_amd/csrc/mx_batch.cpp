@@ -7,7 +7,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <memory>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -212,6 +214,49 @@ int persistent_steps(mx_batch *b, int nsteps, int bin0)
 
 // Time four steps of each candidate plan (pass depth cap x chunk rows) on
 // scratch fields, for the grouped and for the persistent schedule.
+// Modelled length, in row steps, of one sweep pass of a batch whose work
+// items are cut into chunks of L rows for passes at most k deep: each of
+// `slots` resident workgroups claims the next item as it finishes (list
+// scheduling in item order), and an item of r output rows takes r + 3k
+// steps (its pipeline fills and drains k rows per level).  Long chunks pay
+// the fill less often; the item count decides how evenly the last items
+// spread over the workgroups.
+double chunk_makespan(const mx_batch *b, int k, int L, int slots)
+{
+    const int w = cut_width(b->m, k);
+    std::priority_queue<double, std::vector<double>, std::greater<double>> busy;
+    for (int i = 0; i < slots; i++) busy.push(0.0);
+    double end = 0.0;
+    for (const mx_config &c : b->cfg) {
+        const int nx = (int)c.n[0], ny = (int)c.n[1];
+        const int nsx = (nx + w - 1) / w;
+        for (int y0 = 0; y0 < ny; y0 += L)
+            for (int sx = 0; sx < nsx; sx++) {
+                const double t = busy.top() + std::min(L, ny - y0) + 3 * k;
+                busy.pop();
+                busy.push(t);
+                end = std::max(end, t);
+            }
+    }
+    return end;
+}
+
+// chunk lengths to time for passes at most k deep: a fixed set plus the
+// three the model above ranks best (multiples of 8 from 32 to 512)
+std::vector<int> chunk_candidates(const mx_batch *b, int k, int slots)
+{
+    std::vector<int> ls = {64, 128, 256};
+    std::vector<std::pair<double, int>> ranked;
+    for (int L = 32; L <= 512; L += 8) ranked.push_back({chunk_makespan(b, k, L, slots), L});
+    std::sort(ranked.begin(), ranked.end());
+    for (int i = 0, added = 0; i < (int)ranked.size() && added < 3; i++)
+        if (std::find(ls.begin(), ls.end(), ranked[i].second) == ls.end()) {
+            ls.push_back(ranked[i].second);
+            added++;
+        }
+    return ls;
+}
+
 // two timing events, destroyed on every return path
 struct EventPair {
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -231,13 +276,17 @@ int autotune(mx_batch *b, bool grouped, bool persistent)
     const hipEvent_t e0 = ev.e0, e1 = ev.e1;
     // FP32 passes fit two waves per SIMD up to 7 sweeps, FP64 up to 3
     const std::vector<int> ks = sizeof(T) == 4 ? std::vector<int>{4, 5, 6, 7} : std::vector<int>{2, 3, 4};
-    const int ls[] = {48, 64, 96, 128, 192, 256};
     for (int sched = 0; sched < 2; sched++) {
         if ((sched == 0 && !grouped) || (sched == 1 && !persistent)) continue;
         float best = 1e30f;
         int bk = 5, bl = 64;
-        for (int k : ks)
-            for (int l : ls) {
+        for (int k : ks) {
+            int q, npass, nlow;
+            persistent_shape(b->m, k, &q, &npass, &nlow);
+            // resident workgroups: the persistent grid (the grouped
+            // schedule's sweep kernels have the same occupancy)
+            const int slots = batch2d::persistent_blocks<T>(q);
+            for (int l : chunk_candidates(b, k, slots > 0 ? slots : 512)) {
                 int rc = upload<T>(b, true, k, l, l);
                 if (rc) return rc;
                 const int keep[6] = {b->spp, b->Lf, b->Ls, b->pk, b->pLf, b->pLs};
@@ -257,6 +306,7 @@ int autotune(mx_batch *b, bool grouped, bool persistent)
                 BCHK(hipEventElapsedTime(&ms, e0, e1));
                 if (ms < best) { best = ms; bk = k; bl = l; }
             }
+        }
         if (sched == 0) { b->spp = bk; b->Lf = b->Ls = bl; }
         else { b->pk = bk; b->pLf = b->pLs = bl; }
     }
@@ -398,6 +448,28 @@ int mx_batch_get_plan(mx_batch *b, int *sweeps_per_pass, int *tiles_total, int *
         persistent_shape(b->m, b->pk, &q, &npass, &nlow);
         *persistent_blocks = b->dtype == MX_F64 ? batch2d::persistent_blocks<double>(q)
                                                 : batch2d::persistent_blocks<float>(q);
+    }
+    return MX_OK;
+}
+
+int mx_batch_get_schedule(mx_batch *b, int persistent, int *sweeps_per_pass, int *chunk_rows, int *items_per_step)
+{
+    if (!b) return bfail(MX_EINVAL, "batch is NULL");
+    const int k = persistent ? b->pk : b->spp, Lf = persistent ? b->pLf : b->Lf, Ls = persistent ? b->pLs : b->Ls;
+    if (sweeps_per_pass) *sweeps_per_pass = k;
+    if (chunk_rows) *chunk_rows = Ls;
+    if (items_per_step) {
+        // front items, then one set of sweep items per pass
+        std::vector<int> sz;
+        pass_sizes(b->m, k, sz);
+        const int wf = batch2d::front_width(), ws = cut_width(b->m, k);
+        long long n = 0;
+        for (const mx_config &c : b->cfg) {
+            const long long nx = c.n[0], ny = c.n[1];
+            n += ((nx + wf - 1) / wf) * ((ny + Lf - 1) / Lf);
+            n += (long long)sz.size() * ((nx + ws - 1) / ws) * ((ny + Ls - 1) / Ls);
+        }
+        *items_per_step = (int)std::min<long long>(n, 0x7fffffff);
     }
     return MX_OK;
 }

@@ -123,3 +123,11 @@ def test_workspace_size_and_null_workspace():
 def test_step_rejects_null_grid():
     assert mx.lib().mx_step(None, 1, None, None, None) == mx.MX_EINVAL
     assert mx.lib().mx_bind_fields(None, None, None) == mx.MX_EINVAL
+
+
+def test_batch_calls_reject_null_batch():
+    L = mx.lib()
+    assert L.mx_batch_step(None, 1, 0) == mx.MX_EINVAL
+    assert L.mx_batch_get_plan(None, None, None, None) == mx.MX_EINVAL
+    assert L.mx_batch_get_schedule(None, 1, None, None, None) == mx.MX_EINVAL
+    assert L.mx_batch_bind(None, 0, None, None) == mx.MX_EINVAL

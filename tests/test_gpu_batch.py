@@ -122,7 +122,22 @@ def test_batch_full_workload():
     log(f"batch of {len(ws)} grids, {ncell / 1e6:.1f} M cells")
     b1, f1 = _batch(ws, "f32")
     plan = b1.plan()
-    log(f"plan {plan}")
+    sched = {p: b1.schedule(p) for p in (False, True)}
+    log(f"plan {plan}, schedules {sched}")
+    # the tuned shapes are ones the autotuner may pick, and the item count
+    # of a step is the front's plus one set of sweep items per pass
+    m = 20
+    for s in sched.values():
+        k, L = s["sweeps_per_pass"], s["chunk_rows"]
+        assert 4 <= k <= 7 and 32 <= L <= 512
+        npass = -(-m // k)
+        depths = [m // npass + (1 if p_ >= npass - m % npass else 0) for p_ in range(npass)]
+        # 256-column strips: 128-byte aligned runs of 224 columns up to 4
+        # sweeps, 256 - 2k columns above; items are cut with the narrowest
+        ws_cut = min(224 if d <= 4 else 256 - 2 * d for d in depths)
+        want = sum(-(-w.shape[1] // 224) * -(-w.shape[0] // L) + npass * -(-w.shape[1] // ws_cut) * -(-w.shape[0] // L)
+                   for w in ws)
+        assert s["items_per_step"] == want
     b1.step(500, persistent=True)
     b2, f2 = _batch(ws, "f32", plan["sweeps_per_pass"])
     b2.step(500, persistent=False)
