@@ -108,8 +108,12 @@ typedef struct mx_config {
                              delta 9, 4; TM 16 (FP32), 8 (FP64).  LDS tile: <= 8.
                              3D: 1 (library choice) or 2 in FP32, 1 in FP64. */
     int variant;          /* 2D sweep kernel: 0 library choice (FP32: 2, FP64 and
-                             the Chebyshev solve: 3),
-                             1 LDS tile (both blocks per pass), 2 row streaming
+                             the Chebyshev solve: 3; Alg 1 on a grid whose
+                             streaming pass would have fewer workgroups than
+                             half the CUs: 1),
+                             1 LDS tile (both blocks per pass; by default 5
+                             sweeps deep in FP32, 4 in FP64, 8 under a
+                             tolerance), 2 row streaming
                              (both blocks per pass), 3 row streaming (each block
                              on its own) */
     int solver;           /* MX_SOLVER_ALG1 (default) or MX_SOLVER_CHEBYSHEV; the

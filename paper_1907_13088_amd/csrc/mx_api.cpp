@@ -71,7 +71,9 @@ void pass_depths(const mx_config *c, int variant, int out[2])
     }
     const bool f64 = c->dtype == MX_F64;
     if (variant == 1) {
-        const int k = c->sweeps_per_pass > 0 ? c->sweeps_per_pass : (f64 ? 4 : 5);
+        // under a tolerance every pass ends in a host round trip for the
+        // stop test: deeper passes make fewer of them
+        const int k = c->sweeps_per_pass > 0 ? c->sweeps_per_pass : c->tol > 0.0 ? 8 : (f64 ? 4 : 5);
         out[0] = out[1] = k;
         return;
     }
@@ -85,6 +87,24 @@ void pass_depths(const mx_config *c, int variant, int out[2])
         if (tolmode && c->sweeps_per_pass <= 0) k = std::min(kmax[0], kmax[1]);
         out[b] = std::min(k, kmax[b]);
     }
+}
+
+// Workgroups of one row-streaming sweep pass on this grid, as the launcher
+// cuts it (strips of stream_width(k) columns, chunks that fill two
+// workgroups per CU but hold at least 4k rows).
+int stream_workgroups(const mx_config *c, int variant, int ncu)
+{
+    int spp[2];
+    pass_depths(c, variant, spp);
+    const int k = std::max(spp[0], spp[1]);
+    const long long nx = c->n[0], ny = c->n[1];
+    const long long w = mx::stream_width<256>(k);
+    const long long nsx = (nx + w - 1) / w;
+    long long nsy = std::min(std::max(1LL, 2LL * ncu / nsx), ny);
+    long long L = (ny + nsy - 1) / nsy;
+    L = std::max(L, std::min(ny, 4LL * k));
+    nsy = (ny + L - 1) / L;
+    return (int)std::min(nsx * nsy, 0x7fffffffLL);
 }
 
 // number of full-grid arrays in the workspace
@@ -348,9 +368,18 @@ int mx_init(const mx_config *cfg, void *stream, void *workspace, size_t workspac
     // FP64, whose joint passes are only 3 deep, runs each block on its own
     // (TE 5, TM 8 deep), which moves fewer bytes per step; so does the
     // Chebyshev solve (joint passes 5 deep in FP32, per block 8 and 12:
-    // measured 0.46 against 0.60 ms per 4096^2 step at 7 sweeps)
+    // measured 0.46 against 0.60 ms per 4096^2 step at 7 sweeps).  A grid
+    // too small for the row-streaming passes to occupy half the CUs runs
+    // the LDS-tile kernel instead (128^2 to 768^2: 1.4 to 2.8 times faster
+    // per step; the Chebyshev solve has no tile form)
     g->variant = cfg->variant > 0 ? cfg->variant
                                   : (cfg->dtype == MX_F64 || cfg->solver == MX_SOLVER_CHEBYSHEV ? 3 : 2);
+    if (cfg->variant == 0 && cfg->ndim == 2 && cfg->solver != MX_SOLVER_CHEBYSHEV) {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, attr.device) != hipSuccess || cu < 1)
+            cu = 256;
+        if (stream_workgroups(cfg, g->variant, cu) < cu / 2) g->variant = 1;
+    }
     pass_depths(cfg, g->variant, g->spp);
     const size_t arr = up((size_t)g->ncell * elem_of(cfg));
     char *p = g->ws;
