@@ -167,7 +167,11 @@ int mx_set_current(mx_grid *g, void *const J0[3]);
    2*nsteps ints, may be NULL) forces the per-block sweep counts of each
    step instead of the configured rule.  stats (host, nsteps entries, may
    be NULL) receives per-step counts and norms.  Asynchronous on the stream
-   unless tol > 0 (then it waits for each residual check). */
+   unless tol > 0: then the stop test runs on the device after every pass,
+   passes are queued ahead of it (as many per block as the previous step
+   needed; those after convergence do nothing) and the call waits about
+   once per step to read the outcome; a non-finite norm is reported at
+   that read. */
 int mx_step(mx_grid *g, int nsteps, const double *env, const int *replay, mx_step_stats *stats);
 
 /* Step counter n of the bound state. */

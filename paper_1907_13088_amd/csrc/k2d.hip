@@ -61,6 +61,7 @@ __device__ void block_sum2(double &a, double &b, double *sh)
 template <typename T, int BLK, int K, int TX, int TY, bool DELTA>
 __global__ __launch_bounds__(NT) void k2_sweep(Coef<T> c, SweepArgs<T> a, int flags)
 {
+    if (a.skip && *a.skip) return;   // the block has met its stop test
     constexpr int NC = NComp<BLK>::n;
     constexpr int RX = TX + 2 * K, RY = TY + 2 * K, NR = RX * RY;
     constexpr int NS = (NR + NT - 1) / NT;
@@ -187,8 +188,9 @@ __global__ __launch_bounds__(NT) void k_update(int64_t n, int mask, T *E0, T *E1
     if (mask & 4) E2[i] += X2[i];
 }
 
-__global__ __launch_bounds__(NT) void k_reduce2(const double *partial, int nwg, double *out)
+__global__ __launch_bounds__(NT) void k_reduce2(const double *partial, int nwg, double *out, const int *skip)
 {
+    if (skip && *skip) return;   // the pass whose partials these are did not run
     __shared__ double sa[NT], sb[NT];
     double a = 0.0, b = 0.0;
     for (int i = threadIdx.x; i < nwg; i += NT) { a += partial[2 * i]; b += partial[2 * i + 1]; }
@@ -263,9 +265,56 @@ hipError_t launch_update(int64_t n, int mask, T *const E[3], const T *const X[3]
     return hipGetLastError();
 }
 
-hipError_t launch_reduce2(const double *partial, int nwg, double *out, hipStream_t s)
+hipError_t launch_reduce2(const double *partial, int nwg, double *out, hipStream_t s, const int *skip)
 {
-    hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(NT), 0, s, partial, nwg, out);
+    hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(NT), 0, s, partial, nwg, out, skip);
+    return hipGetLastError();
+}
+
+__global__ void k_tol_init(TolState *st, const double *red, int nblk)
+{
+    if (threadIdx.x != 0) return;
+    int bad = 0;
+    for (int b = 0; b < 2; b++) {
+        const double r = b < nblk ? sqrt(red[b]) : 0.0;
+        const bool fin = isfinite(r);
+        if (!fin) bad = 1;
+        st->rhsn[b] = r;
+        st->resid[b] = 0.0;
+        st->skip[b] = (r == 0.0 || !fin) ? 1 : 0;   // dE' = 0: the increment is 0, no sweeps
+        st->done[b] = 0;
+        st->conv[b] = 0;
+        st->last[b] = -1;
+    }
+    st->nonfinite = bad;
+    st->pad = 0;
+}
+
+__global__ void k_tol_decide(TolState *st, const double *red, int b, int k, int buf, double tol)
+{
+    if (threadIdx.x != 0 || st->skip[b]) return;   // the pass did not run
+    st->done[b] += k;
+    st->last[b] = buf;
+    const double r = sqrt(red[b]);
+    st->resid[b] = r;
+    if (!isfinite(r)) {
+        st->nonfinite |= 2;
+        st->skip[b] = 1;
+    } else if (r <= tol * st->rhsn[b]) {
+        st->conv[b] = 1;
+        st->skip[b] = 1;
+    }
+}
+
+hipError_t launch_tol_init(TolState *st, const double *red, int nblk, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tol_init, dim3(1), dim3(64), 0, s, st, red, nblk);
+    return hipGetLastError();
+}
+
+hipError_t launch_tol_decide(TolState *st, const double *red, int b, int k, int buf, double tol, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tol_decide, dim3(1), dim3(64), 0, s, st, red, b, k, buf, tol);
     return hipGetLastError();
 }
 

@@ -384,6 +384,7 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
 template <typename T, int BLK, int K, int FORM, int RX, int OM>
 __global__ __launch_bounds__(RX) void k2_stream(Coef<T> c, SweepArgs<T> a, int flags, int L, int nsx, int nwg)
 {
+    if (a.skip && *a.skip) return;   // the block has met its stop test
     __shared__ __attribute__((aligned(16))) char lds[stream_lds_bytes<T, BLK, K, RX>()];
     __shared__ double sred[2 * RX / 64];
     stream_tile<T, BLK, K, FORM, RX, OM>(c, a, flags, L, nsx, xcd_map(blockIdx.x, nwg), blockIdx.x, lds, sred);

@@ -206,6 +206,7 @@ constexpr int PLOAD = (PCELLS + ZT - 1) / ZT;   // halo-tile cells per thread
 template <typename T, bool DELTA>
 __global__ __launch_bounds__(ZT) void k3_sweep(Coef<T> c, SweepArgs<T> a, int flags, int Lz)
 {
+    if (a.skip && *a.skip) return;   // the solve has met its stop test
     __shared__ T pl[3][3][PY][PX];   // [slot][component][y][x]
     __shared__ double sred[2 * ZT / 64];
     const int nx = c.nx, ny = c.ny, nz = c.nz;
@@ -324,6 +325,7 @@ constexpr int YOX = YX - 4, YOY = YY - 4;
 template <typename T, bool DELTA>
 __global__ __launch_bounds__(YT) void k3_sweep2(Coef<T> c, SweepArgs<T> a, int flags, int Lz)
 {
+    if (a.skip && *a.skip) return;   // the solve has met its stop test
     __shared__ T l0[3][3][YY][YX];   // [slot][component][y][x]
     __shared__ T l1[3][3][YY][YX];
     __shared__ double sred[YT / 64];

@@ -68,6 +68,7 @@ __device__ __forceinline__ void sweep_item(const GridDesc<T> *d, int ng, const i
         sa.E[q] = gd.E[q];
     }
     sa.partial = nullptr;
+    sa.skip = nullptr;
     stream2d::stream_tile<T, 3, K, false, RX, OM>(gd.c, sa, first ? SW_FIRST : 0, L, gd.nsx_s, it - items[g], 0,
                                                   lds, sred);
 }

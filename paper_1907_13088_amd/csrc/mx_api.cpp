@@ -139,7 +139,9 @@ struct mx_grid {
     int bloc[3];          // 2D: where component q of B currently lives (0 user, 1 workspace)
     double *partial;      // device
     double *red;          // device, 2 doubles
-    double *hred = nullptr;   // pinned host copy of red (residual read-back)
+    double *hred = nullptr;   // pinned host memory for read-backs (a TolState)
+    TolState *tol;        // device: the tolerance solve's state within a step
+    int spec[2] = {1, 1}; // passes per block the last tolerance solve ran (queued ahead next step)
     int spp[2];           // sweeps per pass of the TE and TM blocks (3D: [0])
     int variant;          // 2D sweep kernel in use: 1 LDS tile, 2 row streaming (blocks
                           // together), 3 row streaming (each block on its own)
@@ -178,13 +180,13 @@ struct ProfScope {
         e1 = g->ev_pool[g->ev_used + 1];
         g->ev_used += 2;
         g->ev_cat.push_back(cat);
-        hipEventRecord(e0, g->stream);
+        (void)hipEventRecord(e0, g->stream);
         g->launches[cat] += 1;
         g->bytes[cat] += bytes;
     }
     ~ProfScope()
     {
-        if (e1) hipEventRecord(e1, g->stream);
+        if (e1) (void)hipEventRecord(e1, g->stream);
     }
 };
 
@@ -333,7 +335,8 @@ int mx_workspace_size(const mx_config *c, size_t *bytes)
     if (rc) return rc;
     if (!bytes) return fail(MX_EINVAL, "bytes is NULL");
     const size_t arr = up((size_t)ncell_of(c) * elem_of(c));
-    *bytes = n_arrays(c) * arr + up((size_t)max_wg(c) * 2 * sizeof(double)) + up(8 * sizeof(double));
+    *bytes = n_arrays(c) * arr + up((size_t)max_wg(c) * 2 * sizeof(double)) + up(8 * sizeof(double)) +
+             up(sizeof(TolState));
     return MX_OK;
 }
 
@@ -402,15 +405,17 @@ int mx_init(const mx_config *cfg, void *stream, void *workspace, size_t workspac
     g->partial = (double *)p;
     p += up((size_t)max_wg(cfg) * 2 * sizeof(double));
     g->red = (double *)p;
+    p += up(8 * sizeof(double));
+    g->tol = (TolState *)p;
     for (int q = 0; q < 3; q++) { g->E[q] = g->B[q] = g->J0[q] = nullptr; g->bloc[q] = 0; }
     fill_coef(cfg, g->cf);
     fill_coef(cfg, g->cd);
     if (cfg->solver == MX_SOLVER_CHEBYSHEV) fill_cheb(cfg, cfg->sweeps, g->cheb);
-    // 16 bytes of pinned host memory: the tolerance test reads its two FP64
-    // norms back by DMA rather than through a staged pageable copy
-    if (hipHostMalloc((void **)&g->hred, 2 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    // pinned host memory: the tolerance solve reads its state back by DMA
+    // rather than through a staged pageable copy
+    if (hipHostMalloc((void **)&g->hred, sizeof(TolState), hipHostMallocDefault) != hipSuccess) {
         delete g;
-        return fail(MX_EDEVICE, "pinned host buffer of 16 bytes could not be allocated");
+        return fail(MX_EDEVICE, "pinned host buffer of %zu bytes could not be allocated", sizeof(TolState));
     }
     *out = g;
     return MX_OK;
@@ -470,7 +475,7 @@ int mx_get_block_sweeps_per_pass(mx_grid *g, int k[2])
 int mx_destroy(mx_grid *g)
 {
     if (!g) return MX_OK;
-    for (hipEvent_t e : g->ev_pool) hipEventDestroy(e);
+    for (hipEvent_t e : g->ev_pool) (void)hipEventDestroy(e);
     if (g->hred) (void)hipHostFree(g->hred);
     delete g;
     return MX_OK;
@@ -516,31 +521,205 @@ const Coef<double> &coef<double>(const mx_grid *g) { return g->cd; }
 
 int block_mask_comps(int ndim, int b) { return ndim == 3 ? 7 : (b == 0 ? 3 : 4); }
 
-// Run the sweeps of one solve: x = sum_{j<count} A^j b per block (Alg 1).
-// rhs: the right-hand side (dE' or Ebar).  Writes the per-block result
-// pointers into res[3].  When E_fuse is set (fixed count), E += result is
-// fused into a block's final pass and e_done[block] is set.
-//
-// The blocks of a 2D grid are independent: the row-streaming kernel runs the
-// passes of each block on its own (groups {TE}, {TM}); the LDS-tile kernel
-// and 3D run all blocks together (one group).  With a fixed count, a group's
-// m sweeps are cut into the fewest passes of at most spp sweeps, of nearly
-// equal depth (deeper ones last); under a tolerance every pass but the last
-// is spp deep.
+// Sweep arguments of one pass: input iterate buffer cb (-1: the right-hand
+// side itself), output buffer ob; the Chebyshev increments ping-pong with
+// the iterate (a pass reads its neighbours' halo increments, so none is
+// updated in place; before the first sweep there is none: the kernel
+// ignores the values it then reads, which hit the cache lines of dE').
 template <typename T>
-int run_sweeps(mx_grid *g, void *const rhs[3], const int *target_in, bool tolmode, const double *rhsn,
-               void *E_fuse[3], bool e_done[2], const T **res, mx_step_stats *st)
+SweepArgs<T> pass_args(const mx_grid *g, void *const rhs[3], int cb, int ob, bool first, bool cheb,
+                       void *const E_fuse[3])
+{
+    SweepArgs<T> a{};
+    for (int q = 0; q < 3; q++) {
+        a.rhs[q] = (const T *)rhs[q];
+        a.x_in[q] = (const T *)(cb < 0 ? rhs[q] : g->X[cb][q]);
+        a.s_in[q] = (const T *)g->S[q];
+        a.x_out[q] = (T *)g->X[ob][q];
+        a.s_out[q] = (T *)g->S[q];
+        a.E[q] = E_fuse ? (T *)E_fuse[q] : nullptr;
+    }
+    a.partial = g->partial;
+    a.skip = nullptr;
+    if (cheb) {
+        void *const *Din = cb == 1 ? g->D2 : g->S;
+        void *const *Dout = ob == 1 ? g->D2 : g->S;
+        for (int q = 0; q < 3; q++) {
+            a.s_in[q] = (const T *)(first ? rhs[q] : Din[q]);
+            a.s_out[q] = (T *)Dout[q];
+        }
+    }
+    return a;
+}
+
+// Chebyshev factors of a pass of kk sweeps of block b whose first sweep is
+// sweep number `done` of the solve (level l runs sweep done + l)
+template <typename T>
+void pass_cheb(const mx_grid *g, int b, int done, int kk, SweepArgs<T> &a)
+{
+    for (int l = 0; l < kk; l++) {
+        const size_t ix = (size_t)(done + l);
+        const bool ok = ix < g->cheb[b][0].size();
+        a.cheb[b][0][l] = (T)(ok ? g->cheb[b][0][ix] : 0.0);
+        a.cheb[b][1][l] = (T)(ok ? g->cheb[b][1][ix] : 0.0);
+    }
+}
+
+// Arrays a pass touches per component (the algorithmic byte count of the
+// profiler): the iterate (or dE' on the first pass) with halo, dE'
+// (standard form), the running sum (delta form) or the increments
+// (Chebyshev form), the stored iterate, or E read and written.
+int pass_arrays(bool cheb, bool delta, bool first, bool last)
+{
+    if (cheb) return (first ? 1 : 3) + 2;
+    if (!delta) return (first ? 1 : 2) + (last ? 2 : 1);
+    return (first ? 1 : 2) + 2;
+}
+
+// Tolerance solve: Alg 1 (or the Chebyshev solve) with the stop test of
+// each block.  Each block runs in passes of its own (2D: TE and TM; 3D: one
+// block), of spp sweeps (the last one shorter where m_max ends the
+// count).  Passes are queued ahead of the stop test: each is followed
+// by the reduction of its step norm and the test on the device, which makes
+// the passes queued after it do nothing once the block has converged.  The
+// host reads the state back when the queued passes of every block have run:
+// first as many per block as it ran at the previous step, then one more at
+// a time.  The sweep counts and iterates equal those of testing after every
+// pass on the host; the host waits about once per step instead of once per
+// pass.
+template <typename T>
+int solve_tol(mx_grid *g, void *const rhs[3], const int *target_in, const T **res, mx_step_stats *st)
 {
     const mx_config &c = g->cfg;
     const Coef<T> &k = coef<T>(g);
     const int nblk = c.ndim == 3 ? 1 : 2;
-    const bool delta = c.form == MX_FORM_DELTA && tolmode;
+    const bool delta = c.form == MX_FORM_DELTA;
     const bool cheb = c.solver == MX_SOLVER_CHEBYSHEV;
     const int form = cheb ? FM_CHEB : delta ? FM_DELTA : FM_STD;
+    bool active[2] = {false, false};
+    int target[2] = {0, 0};
+    for (int b = 0; b < nblk; b++) {
+        active[b] = c.ndim == 3 || (c.blocks & (1 << b));
+        target[b] = active[b] ? target_in[b] : 0;
+    }
+    if (cheb && (int)g->cheb[0][0].size() < std::max(target[0], target[1]))
+        fill_cheb(&c, std::max(target[0], target[1]), g->cheb);
+    TolState *hs = (TolState *)g->hred;
+    bool have = false;
+    auto read_back = [&]() -> int {
+        HIPCHK(hipMemcpyAsync(hs, g->tol, sizeof(TolState), hipMemcpyDeviceToHost, g->stream));
+        HIPCHK(hipStreamSynchronize(g->stream));
+        have = true;
+        if (hs->nonfinite & 1)
+            return fail(MX_ENONFINITE, "step %lld: norm of dE' is not finite", (long long)g->step);
+        if (hs->nonfinite & 2)
+            return fail(MX_ENONFINITE, "step %lld: a residual norm is not finite", (long long)g->step);
+        return MX_OK;
+    };
+    int enq[2] = {0, 0}, swe[2] = {0, 0}, ahead[2];
+    bool open[2];
+    for (int b = 0; b < 2; b++) {
+        ahead[b] = std::max(1, g->spec[b]);
+        open[b] = b < nblk && target[b] > 0;
+    }
+    for (;;) {
+        bool any = false;
+        for (int b = 0; b < nblk; b++) {
+            if (!open[b]) continue;
+            any = true;
+            const int spp = g->spp[b];
+            const int *skip = &g->tol->skip[b];
+            while (enq[b] < ahead[b] && swe[b] < target[b]) {
+                const int kk = std::min(spp, target[b] - swe[b]);
+                const bool first = enq[b] == 0;
+                const int cb = first ? -1 : (enq[b] - 1) & 1, ob = enq[b] & 1;
+                SweepArgs<T> a = pass_args<T>(g, rhs, cb, ob, first, cheb, nullptr);
+                a.skip = skip;
+                if (cheb) pass_cheb<T>(g, b, swe[b], kk, a);
+                const int flags = (first ? SW_FIRST : 0) | SW_RESID | SW_STORE;
+                int nwg = 0;
+                hipError_t e;
+                {
+                    const int ncomp = c.ndim == 3 ? 3 : (b == 0 ? 2 : 1);
+                    ProfScope ps(g, MX_PROF_SWEEP,
+                                 (double)g->ncell * sizeof(T) * pass_arrays(cheb, delta, first, false) * ncomp);
+                    if (c.ndim == 2 && g->variant == 1)
+                        e = launch_sweep2d<T>(k, 1 << b, kk, delta, flags, a, g->stream, &nwg);
+                    else if (c.ndim == 2)
+                        e = launch_stream2d<T>(k, 1 << b, kk, form, flags, a, g->stream, &nwg, 0);
+                    else
+                        e = launch_sweep3d<T>(k, kk, delta, flags, a, g->stream, &nwg);
+                }
+                if (e != hipSuccess) return fail(MX_EDEVICE, "sweep launch: %s", hipGetErrorString(e));
+                {
+                    ProfScope ps(g, MX_PROF_OTHER, 0.0);
+                    HIPCHK(launch_reduce2(g->partial, nwg, g->red, g->stream, skip));
+                    HIPCHK(launch_tol_decide(g->tol, g->red, b, kk, ob, c.tol, g->stream));
+                }
+                enq[b]++;
+                swe[b] += kk;
+            }
+        }
+        if (!any) break;
+        const int rc = read_back();
+        if (rc) return rc;
+        for (int b = 0; b < nblk; b++) {
+            if (!open[b]) continue;
+            if (hs->skip[b] || swe[b] >= target[b]) {
+                open[b] = false;
+                // passes the block ran: queued ahead at the next step
+                g->spec[b] = std::max(1, (hs->done[b] + g->spp[b] - 1) / g->spp[b]);
+            } else {
+                ahead[b] = enq[b] + 1;
+            }
+        }
+    }
+    if (!have) {
+        const int rc = read_back();   // no block ran: the norms of dE' for the stats
+        if (rc) return rc;
+    }
+    for (int q = 0; q < 3; q++) {
+        const int b = c.ndim == 3 ? 0 : (q == 2 ? 1 : 0);
+        if (hs->done[b] == 0) res[q] = (const T *)rhs[q];
+        else res[q] = delta ? (const T *)g->S[q] : (const T *)g->X[hs->last[b]][q];
+    }
+    if (st) {
+        for (int b = 0; b < 2; b++) {
+            st->sweeps[b] = hs->done[b];
+            st->resid[b] = hs->resid[b];
+            st->rhs[b] = hs->rhsn[b];
+            st->nonconverged[b] = active[b] && hs->done[b] > 0 && !hs->conv[b] ? 1 : 0;
+        }
+    }
+    return MX_OK;
+}
+
+// Run the sweeps of one solve: x = sum_{j<count} A^j b per block (Alg 1).
+// rhs: the right-hand side (dE' or Ebar).  Writes the per-block result
+// pointers into res[3].  When E_fuse is set (fixed count), E += result is
+// fused into a block's final pass and e_done[block] is set.  A tolerance
+// solve (tolmode) is solve_tol's.
+//
+// The blocks of a 2D grid are independent: the row-streaming kernel runs the
+// passes of each block on its own (groups {TE}, {TM}); the LDS-tile kernel
+// and 3D run all blocks together (one group).  A group's count of sweeps is
+// cut into the fewest passes of at most spp sweeps, of nearly equal depth
+// (deeper ones last: the final pass also reads and writes E, so its sweeps
+// are the cheapest).
+template <typename T>
+int run_sweeps(mx_grid *g, void *const rhs[3], const int *target_in, bool tolmode, void *E_fuse[3],
+               bool e_done[2], const T **res, mx_step_stats *st)
+{
+    e_done[0] = e_done[1] = false;
+    if (tolmode) return solve_tol<T>(g, rhs, target_in, res, st);
+    const mx_config &c = g->cfg;
+    const Coef<T> &k = coef<T>(g);
+    const int nblk = c.ndim == 3 ? 1 : 2;
+    const bool cheb = c.solver == MX_SOLVER_CHEBYSHEV;
+    const int form = cheb ? FM_CHEB : FM_STD;
     const bool split = c.ndim == 2 && g->variant == 3;
     int target[2] = {0, 0}, done[2] = {0, 0}, cur[2] = {-1, -1};
-    bool conv[2] = {false, false}, fused[2] = {false, false};
-    double resid[2] = {0.0, 0.0};
+    bool fused[2] = {false, false};
     bool active_cfg[2];
     for (int b = 0; b < 2; b++) {
         active_cfg[b] = b < nblk && (c.ndim == 3 || (c.blocks & (1 << b)));
@@ -555,109 +734,53 @@ int run_sweeps(mx_grid *g, void *const rhs[3], const int *target_in, bool tolmod
         for (;;) {
             int act = 0, rem = 1 << 30;
             for (int b = 0; b < nblk; b++)
-                if ((gmask & (1 << b)) && active_cfg[b] && done[b] < target[b] && !conv[b]) {
+                if ((gmask & (1 << b)) && active_cfg[b] && done[b] < target[b]) {
                     act |= 1 << b;
                     rem = std::min(rem, target[b] - done[b]);
                 }
             if (!act) break;
             const int spp = (act & 1) ? g->spp[0] : g->spp[1];
-            // fixed count: the fewest passes, the deeper ones last (the final
-            // pass also reads and writes E, so its sweeps are the cheapest)
-            const int kk = tolmode ? std::min(rem, spp) : rem / ((rem + spp - 1) / spp);
+            const int kk = rem / ((rem + spp - 1) / spp);
             const bool first = (act & 1) ? done[0] == 0 : done[1] == 0;
             // E += x fused into this pass when every active block of the group ends here
-            bool fin = !tolmode && E_fuse != nullptr;
+            bool fin = E_fuse != nullptr;
             for (int b = 0; b < nblk; b++) {
                 if (!(gmask & (1 << b)) || !active_cfg[b]) continue;
                 if (!(act & (1 << b)) || done[b] + kk != target[b]) fin = false;
             }
-            int flags = 0;
-            if (first) flags |= SW_FIRST;
-            if (tolmode) flags |= SW_RESID;
-            if (fin) flags |= SW_LAST; else flags |= SW_STORE;
+            int flags = first ? SW_FIRST : 0;
+            flags |= fin ? SW_LAST : SW_STORE;
             const int cb = (act & 1) ? cur[0] : cur[1];
             const int ob = cb == 0 ? 1 : 0;
-            SweepArgs<T> a{};
-            for (int q = 0; q < 3; q++) {
-                a.rhs[q] = (const T *)rhs[q];
-                a.x_in[q] = (const T *)(cb < 0 ? rhs[q] : g->X[cb][q]);
-                a.s_in[q] = (const T *)g->S[q];
-                a.x_out[q] = (T *)g->X[ob][q];
-                a.s_out[q] = (T *)g->S[q];
-                a.E[q] = E_fuse ? (T *)E_fuse[q] : nullptr;
-            }
-            a.partial = g->partial;
-            if (cheb) {
-                // increments ping-pong with the iterate (a pass reads its
-                // neighbours' halo increments, so none is updated in place);
-                // none before the first sweep: the kernel ignores the values
-                // it reads then, which hit the cache lines of dE'
-                void *const *Din = cb == 1 ? g->D2 : g->S;
-                void *const *Dout = ob == 1 ? g->D2 : g->S;
-                for (int q = 0; q < 3; q++) {
-                    a.s_in[q] = (const T *)(first ? rhs[q] : Din[q]);
-                    a.s_out[q] = (T *)Dout[q];
-                }
-                // factors of the pass's sweeps: level l runs sweep done[b] + l - 1
-                for (int b = 0; b < 2; b++)
-                    for (int l = 0; l < kk; l++) {
-                        const size_t ix = (size_t)(done[b] + l);
-                        const bool ok = ix < g->cheb[b][0].size();
-                        a.cheb[b][0][l] = (T)(ok ? g->cheb[b][0][ix] : 0.0);
-                        a.cheb[b][1][l] = (T)(ok ? g->cheb[b][1][ix] : 0.0);
-                    }
-            }
+            SweepArgs<T> a = pass_args<T>(g, rhs, cb, ob, first, cheb, E_fuse);
+            if (cheb)
+                for (int b = 0; b < 2; b++) pass_cheb<T>(g, b, done[b], kk, a);
             int nwg = 0;
             hipError_t e;
             {
-                // arrays touched per component: the iterate (or dE' on the first
-                // pass) with halo, dE' (standard form), the running sum (delta
-                // form), the stored iterate/sum, or E read and written
-                int arrs;
-                if (cheb) arrs = (first ? 1 : 3) + 2;
-                else if (!delta) arrs = (first ? 1 : 2) + ((flags & SW_LAST) ? 2 : 1);
-                else arrs = (first ? 1 : 2) + ((flags & SW_LAST) ? 2 : 2);
                 const int ncomp = c.ndim == 3 ? 3 : ((act & 1) ? 2 : 0) + ((act & 2) ? 1 : 0);
-                ProfScope ps(g, (flags & SW_LAST) ? MX_PROF_SWEEP_LAST : MX_PROF_SWEEP,
-                             (double)g->ncell * sizeof(T) * arrs * ncomp);
-                if (c.ndim == 2 && g->variant == 1) e = launch_sweep2d<T>(k, act, kk, delta, flags, a, g->stream, &nwg);
+                ProfScope ps(g, fin ? MX_PROF_SWEEP_LAST : MX_PROF_SWEEP,
+                             (double)g->ncell * sizeof(T) * pass_arrays(cheb, false, first, fin) * ncomp);
+                if (c.ndim == 2 && g->variant == 1) e = launch_sweep2d<T>(k, act, kk, false, flags, a, g->stream, &nwg);
                 else if (c.ndim == 2) e = launch_stream2d<T>(k, act, kk, form, flags, a, g->stream, &nwg, 0);
-                else e = launch_sweep3d<T>(k, kk, delta, flags, a, g->stream, &nwg);
+                else e = launch_sweep3d<T>(k, kk, false, flags, a, g->stream, &nwg);
             }
             if (e != hipSuccess) return fail(MX_EDEVICE, "sweep launch: %s", hipGetErrorString(e));
             for (int b = 0; b < nblk; b++)
                 if (act & (1 << b)) { done[b] += kk; cur[b] = ob; fused[b] = fin; }
-            if (tolmode) {
-                {
-                    ProfScope ps(g, MX_PROF_OTHER, 0.0);
-                    HIPCHK(launch_reduce2(g->partial, nwg, g->red, g->stream));
-                }
-                double *h = g->hred;
-                HIPCHK(hipMemcpyAsync(h, g->red, 2 * sizeof(double), hipMemcpyDeviceToHost, g->stream));
-                HIPCHK(hipStreamSynchronize(g->stream));
-                for (int b = 0; b < nblk; b++) {
-                    if (!(act & (1 << b))) continue;
-                    resid[b] = std::sqrt(h[b]);
-                    if (!std::isfinite(resid[b]))
-                        return fail(MX_ENONFINITE, "step %lld: residual of block %d is not finite",
-                                    (long long)g->step, b);
-                    if (resid[b] <= c.tol * rhsn[b]) conv[b] = true;
-                }
-            }
         }
     }
     for (int b = 0; b < 2; b++) e_done[b] = fused[b];
     for (int q = 0; q < 3; q++) {
         const int b = c.ndim == 3 ? 0 : (q == 2 ? 1 : 0);
-        if (done[b] == 0) res[q] = (const T *)rhs[q];
-        else res[q] = delta ? (const T *)g->S[q] : (const T *)g->X[cur[b]][q];
+        res[q] = done[b] == 0 ? (const T *)rhs[q] : (const T *)g->X[cur[b]][q];
     }
     if (st) {
         for (int b = 0; b < 2; b++) {
             st->sweeps[b] = done[b];
-            st->resid[b] = resid[b];
-            st->rhs[b] = rhsn ? rhsn[b] : 0.0;
-            st->nonconverged[b] = tolmode && active_cfg[b] && done[b] > 0 && !conv[b] ? 1 : 0;
+            st->resid[b] = 0.0;
+            st->rhs[b] = 0.0;
+            st->nonconverged[b] = 0;
         }
     }
     return MX_OK;
@@ -674,7 +797,6 @@ int step_impl(mx_grid *g, int nsteps, const double *env, const int *replay, mx_s
         const double e = env ? env[s] : 0.0;
         const T env_src = (T)(e * c.four_pi * c.dt);
         int nwg = 0;
-        double rhsn[2] = {0.0, 0.0};
         if (c.ndim == 2) {
             const T *Bin[3];
             T *Bout[3];
@@ -728,31 +850,21 @@ int step_impl(mx_grid *g, int nsteps, const double *env, const int *replay, mx_s
             if (er != hipSuccess) return fail(MX_EDEVICE, "rhs launch: %s", hipGetErrorString(er));
         }
         if (tolmode) {
-            {
-                ProfScope ps(g, MX_PROF_OTHER, 0.0);
-                HIPCHK(launch_reduce2(g->partial, nwg, g->red, g->stream));
-            }
-            double *h = g->hred;
-            HIPCHK(hipMemcpyAsync(h, g->red, 2 * sizeof(double), hipMemcpyDeviceToHost, g->stream));
-            HIPCHK(hipStreamSynchronize(g->stream));
-            for (int b = 0; b < nblk; b++) {
-                rhsn[b] = std::sqrt(h[b]);
-                if (!std::isfinite(rhsn[b]))
-                    return fail(MX_ENONFINITE, "step %lld: norm of dE' is not finite", (long long)g->step);
-            }
+            // ||dE'|| per block starts the device-side state of the solve
+            ProfScope ps(g, MX_PROF_OTHER, 0.0);
+            HIPCHK(launch_reduce2(g->partial, nwg, g->red, g->stream));
+            HIPCHK(launch_tol_init(g->tol, g->red, nblk, g->stream));
         }
         int target[2];
         for (int b = 0; b < 2; b++) {
             target[b] = replay ? replay[2 * s + b] : c.sweeps;
             if (!replay && c.lumped) target[b] = 0;
-            if (tolmode && rhsn[b] == 0.0) target[b] = 0;
             if (target[b] < 0) return fail(MX_EINVAL, "negative replayed sweep count at step %d", s);
         }
         const T *res[3];
         bool e_done[2] = {false, false};
         mx_step_stats st{};
-        int rc = run_sweeps<T>(g, g->dEp, target, tolmode, rhsn, g->E, e_done, res,
-                               stats ? &st : nullptr);
+        int rc = run_sweeps<T>(g, g->dEp, target, tolmode, g->E, e_done, res, stats ? &st : nullptr);
         if (rc) return rc;
         {
             // E += dE per block not fused into its last pass (the components
@@ -809,7 +921,7 @@ int adjoint_impl(mx_grid *g, int nsteps, const double *env, const int *sweeps, v
         const T *v[3];
         bool e_done[2] = {false, false};
         // v = P Ebar
-        int rc = run_sweeps<T>(g, Ebar, target, false, nullptr, nullptr, e_done, v, nullptr);
+        int rc = run_sweeps<T>(g, Ebar, target, false, nullptr, e_done, v, nullptr);
         if (rc) return rc;
         {
             ProfScope ps(g, MX_PROF_ADJOINT, arr * 9);

@@ -63,9 +63,28 @@ struct SweepArgs {
     T *s_out[3];
     T *E[3];
     double *partial;      // per-workgroup partial sums [nblocks][2] (TE, TM)
+    // tolerance solve: the pass does nothing when *skip is set (its block
+    // has met the stop test on the device); null: always run
+    const int *skip;
     // Chebyshev form: per block (TE, TM) and sweep level of the pass, the
     // factors of the previous increment and of the residual
     T cheb[2][2][16];
+};
+
+// Device-side state of a tolerance solve within one step, per block (2D:
+// TE, TM; 3D: block 0).  Passes of a block are queued ahead of the stop
+// test; each pass's norm is reduced and tested on the device, which sets
+// skip[b] once the block has converged (or has no work, or a norm is not
+// finite), so the passes queued after it do nothing.
+struct TolState {
+    double rhsn[2];       // ||dE'|| per block
+    double resid[2];      // ||x_(j+1) - x_j|| of the last pass run
+    int skip[2];          // 1: further passes of the block do nothing
+    int done[2];          // sweeps run
+    int conv[2];          // met resid <= tol * rhsn
+    int last[2];          // iterate buffer the last pass run wrote (-1: none)
+    int nonfinite;        // bit 0: ||dE'||, bit 1: a residual
+    int pad;
 };
 
 // Iterate forms of the 2D streaming sweep pass (compile time)
@@ -208,7 +227,12 @@ hipError_t launch_sweep3d(const Coef<T> &c, int k, bool delta, int flags, const 
                           hipStream_t s, int *nwg);
 
 // FP64 partial-sum reduction: out[0..1] = sum over nwg rows of partial[row][0..1]
-hipError_t launch_reduce2(const double *partial, int nwg, double *out, hipStream_t s);
+hipError_t launch_reduce2(const double *partial, int nwg, double *out, hipStream_t s, const int *skip = nullptr);
+// tolerance solve state: start a step from the reduced ||dE'||^2 per block
+hipError_t launch_tol_init(TolState *st, const double *red, int nblk, hipStream_t s);
+// after a pass of k sweeps of block b that wrote iterate buffer buf: the
+// reduced step norm, the stop test against tol * ||dE'||
+hipError_t launch_tol_decide(TolState *st, const double *red, int b, int k, int buf, double tol, hipStream_t s);
 
 // Adjoint helpers (kadj.hip)
 template <typename T>
