@@ -15,7 +15,7 @@ import pytest
 from paper_1907_13088_amd import inputs as I
 from paper_1907_13088_amd import mx
 
-from gpu_helpers import gpu_config, log, rel_err, run_gpu, run_oracle
+from gpu_helpers import gpu_config, log, rel_err, run_gpu, run_oracle, to_np, torch_fields
 
 pytestmark = pytest.mark.gpu
 
@@ -338,3 +338,51 @@ def test_full_size_modes_sampled_windows_in_bench_configuration():
             e = rel_err(got, [a[s0, s0] for a in Eo + Bo])
             log(f"window at ({cy}, {cx}): {dt_} GPU vs FP64 oracle {max(e):.2e}")
             assert max(e) < tol, (dt_, cy, cx, e)
+
+
+@pytest.mark.parametrize("variant,dtype,form", [(mx.VARIANT_TILE, "f64", mx.FORM_STANDARD),
+                                                (mx.VARIANT_STREAM, "f64", mx.FORM_STANDARD),
+                                                (mx.VARIANT_STREAM_BLOCK, "f64", mx.FORM_STANDARD),
+                                                (mx.VARIANT_STREAM, "f32", mx.FORM_STANDARD)])
+def test_tolerance_solve_equals_replay_of_its_own_counts(variant, dtype, form):
+    """The stop test runs on the device and gates passes queued ahead of it
+    (as many as the block needed at the previous step).  The first step
+    grows its queue one pass per read-back; a pulsed current then makes the
+    counts fall (queued passes left over) and, in FP64, rise again (passes
+    added after a read-back); either way the fields equal, bitwise, a run
+    that replays the counts the solve chose.  (Replays run the standard
+    form, so the delta form has no bitwise replay.)"""
+    import torch
+    ny, nx = 72, 96
+    dt = 0.7 / math.sqrt(2.0)
+    rng = np.random.default_rng(77)
+    E0 = [rng.normal(size=(ny, nx)) for _ in range(3)]
+    B0 = [rng.normal(size=(ny, nx)) for _ in range(3)]
+    J0 = [rng.normal(size=(ny, nx)) for _ in range(3)]
+    env = [0.0, 40.0, 0.0, 0.0, 40.0, 0.0, 40.0, 40.0]
+    tol = 1e-10 if dtype == "f64" else 1e-6
+
+    def run(replay):
+        cfg = mx.make_config(2, (nx, ny), dt, (1.0, 1.0), dtype, mx.MX_ALL, 400, tol, 1, form=form,
+                             variant=variant)
+        g = mx.Grid(cfg)
+        E, B, J = torch_fields(E0, dtype), torch_fields(B0, dtype), torch_fields(J0, dtype)
+        g.bind(E, B)
+        g.set_current(J)
+        st = []
+        for s in range(len(env)):   # one call per step: the queue depth follows the previous step
+            st += g.step(1, env=[env[s]], replay=None if replay is None else [replay[s]], stats=True)
+        torch.cuda.synchronize()
+        out = to_np(E + B)
+        g.close()
+        return out, [tuple(x.sweeps) for x in st], st
+
+    own, counts, st = run(None)
+    log(f"variant={variant} {dtype} form={form}: counts {counts}")
+    assert not any(any(x.nonconverged) for x in st)
+    assert any(counts[s][b] < counts[s - 1][b] for s in range(1, len(counts)) for b in (0, 1))
+    if dtype == "f64":
+        assert any(counts[s][b] > counts[s - 1][b] for s in range(1, len(counts)) for b in (0, 1))
+    rep, _, _ = run(counts)
+    for a, b in zip(own, rep):
+        assert np.array_equal(a, b)
