@@ -18,8 +18,8 @@
  * Memory model.  The caller owns every byte of device memory: field
  * buffers are borrowed device pointers and the library's scratch lives in a
  * caller-provided workspace of mx_workspace_size() bytes.  The library never
- * allocates device memory (mx_init takes 16 bytes of pinned host memory, to
- * read the tolerance test's norms back).  All kernels run on the HIP stream
+ * allocates device memory (mx_init takes 80 bytes of pinned host memory, to
+ * read the tolerance solve's state back).  All kernels run on the HIP stream
  * given to mx_init (NULL = the default stream).
  *
  * Layout.  Each field component is one dense array in the grid dtype
