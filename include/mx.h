@@ -276,10 +276,12 @@ int mx_batch_step(mx_batch *b, int nsteps, int persistent);
    of one step, and the workgroups of the persistent launch. */
 int mx_batch_get_plan(mx_batch *b, int *sweeps_per_pass, int *tiles_total, int *persistent_blocks);
 /* One schedule's tuned shape (persistent = 0 grouped, 1 persistent): the
-   deepest pass (sweeps), the rows of a work item's chunk and the work items
-   of one step (front plus sweep passes).  Any output pointer may be NULL.
-   Host only; MX_EINVAL for a NULL batch. */
-int mx_batch_get_schedule(mx_batch *b, int persistent, int *sweeps_per_pass, int *chunk_rows, int *items_per_step);
+   deepest pass (sweeps), the rows of a sweep work item's chunk and of a
+   front work item's, and the work items of one step (front plus sweep
+   passes).  Any output pointer may be NULL.  Host only; MX_EINVAL for a
+   NULL batch. */
+int mx_batch_get_schedule(mx_batch *b, int persistent, int *sweeps_per_pass, int *chunk_rows, int *front_rows,
+                          int *items_per_step);
 int mx_batch_destroy(mx_batch *b);
 
 #ifdef __cplusplus

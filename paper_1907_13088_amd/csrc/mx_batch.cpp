@@ -307,8 +307,32 @@ int autotune(mx_batch *b, bool grouped, bool persistent)
                 if (ms < best) { best = ms; bk = k; bl = l; }
             }
         }
-        if (sched == 0) { b->spp = bk; b->Lf = b->Ls = bl; }
-        else { b->pk = bk; b->pLf = b->pLs = bl; }
+        // the front phase's chunk rows on their own, with the chosen sweeps
+        int blf = bl;
+        for (int lf : {64, 128, 256}) {
+            if (lf == bl) continue;
+            int rc = upload<T>(b, true, bk, lf, bl);
+            if (rc) return rc;
+            const int keep[6] = {b->spp, b->Lf, b->Ls, b->pk, b->pLf, b->pLs};
+            b->spp = b->pk = bk;
+            b->Lf = b->pLf = lf;
+            b->Ls = b->pLs = bl;
+            rc = sched == 0 ? grouped_steps<T>(b, 1, 0) : persistent_steps<T>(b, 1, 0);   // warm
+            if (!rc) {
+                BCHK(hipEventRecord(e0, b->stream));
+                rc = sched == 0 ? grouped_steps<T>(b, 4, 0) : persistent_steps<T>(b, 4, 0);
+                BCHK(hipEventRecord(e1, b->stream));
+            }
+            b->spp = keep[0]; b->Lf = keep[1]; b->Ls = keep[2];
+            b->pk = keep[3]; b->pLf = keep[4]; b->pLs = keep[5];
+            if (rc) return rc;
+            BCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            BCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) { best = ms; blf = lf; }
+        }
+        if (sched == 0) { b->spp = bk; b->Lf = blf; b->Ls = bl; }
+        else { b->pk = bk; b->pLf = blf; b->pLs = bl; }
     }
     return MX_OK;
 }
@@ -452,12 +476,14 @@ int mx_batch_get_plan(mx_batch *b, int *sweeps_per_pass, int *tiles_total, int *
     return MX_OK;
 }
 
-int mx_batch_get_schedule(mx_batch *b, int persistent, int *sweeps_per_pass, int *chunk_rows, int *items_per_step)
+int mx_batch_get_schedule(mx_batch *b, int persistent, int *sweeps_per_pass, int *chunk_rows, int *front_rows,
+                          int *items_per_step)
 {
     if (!b) return bfail(MX_EINVAL, "batch is NULL");
     const int k = persistent ? b->pk : b->spp, Lf = persistent ? b->pLf : b->Lf, Ls = persistent ? b->pLs : b->Ls;
     if (sweeps_per_pass) *sweeps_per_pass = k;
     if (chunk_rows) *chunk_rows = Ls;
+    if (front_rows) *front_rows = Lf;
     if (items_per_step) {
         // front items, then one set of sweep items per pass
         std::vector<int> sz;

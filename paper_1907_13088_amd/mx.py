@@ -98,7 +98,7 @@ def lib():
             L.mx_batch_bind.argtypes = [vp, C.c_int, P(vp), P(vp)]
             L.mx_batch_step.argtypes = [vp, C.c_int, C.c_int]
             L.mx_batch_get_plan.argtypes = [vp, P(C.c_int), P(C.c_int), P(C.c_int)]
-            L.mx_batch_get_schedule.argtypes = [vp, C.c_int, P(C.c_int), P(C.c_int), P(C.c_int)]
+            L.mx_batch_get_schedule.argtypes = [vp, C.c_int, P(C.c_int), P(C.c_int), P(C.c_int), P(C.c_int)]
             L.mx_batch_destroy.argtypes = [vp]
         _lib = L
     return _lib
@@ -337,11 +337,12 @@ class Batch:
         return {"sweeps_per_pass": a.value, "tiles": b.value, "persistent_blocks": c.value}
 
     def schedule(self, persistent):
-        """The tuned shape of one schedule: deepest pass, chunk rows, work
-        items of one step."""
-        a, b, c = C.c_int(), C.c_int(), C.c_int()
-        _check(lib().mx_batch_get_schedule(self.h, int(bool(persistent)), C.byref(a), C.byref(b), C.byref(c)))
-        return {"sweeps_per_pass": a.value, "chunk_rows": b.value, "items_per_step": c.value}
+        """The tuned shape of one schedule: deepest pass, chunk rows of the
+        sweep and of the front work items, work items of one step."""
+        a, b, f, c = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        _check(lib().mx_batch_get_schedule(self.h, int(bool(persistent)), C.byref(a), C.byref(b), C.byref(f),
+                                           C.byref(c)))
+        return {"sweeps_per_pass": a.value, "chunk_rows": b.value, "front_rows": f.value, "items_per_step": c.value}
 
     def close(self):
         if getattr(self, "h", None):

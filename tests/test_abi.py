@@ -129,5 +129,5 @@ def test_batch_calls_reject_null_batch():
     L = mx.lib()
     assert L.mx_batch_step(None, 1, 0) == mx.MX_EINVAL
     assert L.mx_batch_get_plan(None, None, None, None) == mx.MX_EINVAL
-    assert L.mx_batch_get_schedule(None, 1, None, None, None) == mx.MX_EINVAL
+    assert L.mx_batch_get_schedule(None, 1, None, None, None, None) == mx.MX_EINVAL
     assert L.mx_batch_bind(None, 0, None, None) == mx.MX_EINVAL

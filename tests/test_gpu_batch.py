@@ -128,14 +128,14 @@ def test_batch_full_workload():
     # of a step is the front's plus one set of sweep items per pass
     m = 20
     for s in sched.values():
-        k, L = s["sweeps_per_pass"], s["chunk_rows"]
-        assert 4 <= k <= 7 and 32 <= L <= 512
+        k, L, Lf = s["sweeps_per_pass"], s["chunk_rows"], s["front_rows"]
+        assert 4 <= k <= 7 and 32 <= L <= 512 and 32 <= Lf <= 512
         npass = -(-m // k)
         depths = [m // npass + (1 if p_ >= npass - m % npass else 0) for p_ in range(npass)]
         # 256-column strips: 128-byte aligned runs of 224 columns up to 4
         # sweeps, 256 - 2k columns above; items are cut with the narrowest
         ws_cut = min(224 if d <= 4 else 256 - 2 * d for d in depths)
-        want = sum(-(-w.shape[1] // 224) * -(-w.shape[0] // L) + npass * -(-w.shape[1] // ws_cut) * -(-w.shape[0] // L)
+        want = sum(-(-w.shape[1] // 224) * -(-w.shape[0] // Lf) + npass * -(-w.shape[1] // ws_cut) * -(-w.shape[0] // L)
                    for w in ws)
         assert s["items_per_step"] == want
     b1.step(500, persistent=True)
