@@ -309,11 +309,13 @@ static double norm2_mask(const ora_cfg *c, double *const a[3], double *const b[3
 /* bilinear in (sx, sy), so its maximum is at a corner of [0,1]^2; the 2D TE */
 /* symbol is the 2x2 matrix [[(2/3)(1-ry) sy, m], [m, (2/3)(1-rx) sx]] with  */
 /* m^2 = (4/9) rx ry sx sy, whose largest eigenvalue peaks at sx = sy = 1,   */
-/* where it is 2/3 for any dt.                                               */
+/* where it is 2/3 for any dt.  In 3D with cubic cells the spectrum of the   */
+/* coupled 3x3 symbol fills [0, 8/9] for any dt.                             */
 /* ------------------------------------------------------------------------ */
 static double spectrum_top(const ora_cfg *c, int blk)
 {
     double rx = c->dt * c->dt / (c->dx * c->dx), ry = c->dt * c->dt / (c->dy * c->dy);
+    if (c->ndim == 3) return 8.0 / 9.0;
     if (blk == 0) return 2.0 / 3.0;
     double a = 2.0 / 3.0 * (1.0 - rx), b = 2.0 / 3.0 * (1.0 - ry), d = 8.0 / 9.0 - 2.0 / 9.0 * (rx + ry);
     double m = a > b ? a : b;

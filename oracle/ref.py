@@ -80,8 +80,8 @@ class Config:
     solver: int = 0                 # 0: Alg 1; 1: Chebyshev semi-iteration
 
     def c(self) -> _Cfg:
-        if self.solver != 0 and self.ndim != 2:
-            raise ValueError("the Chebyshev solve is defined for 2D grids only")
+        if self.solver != 0 and self.ndim == 3 and not (self.d[0] == self.d[1] == self.d[2]):
+            raise ValueError("the 3D Chebyshev solve is defined for cubic cells only")
         if self.ndim == 2:
             ny, nx = self.shape
             nz = 1

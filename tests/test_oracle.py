@@ -725,3 +725,43 @@ def test_chebyshev_error_bound():
         x, _ = ref.solve(ref.Config(ndim=2, shape=shape, dt=dt, d=d, blocks=2, sweeps=k, solver=1), b)
         bound = e0 / np.polynomial.chebyshev.chebval(theta / delta, [0] * k + [1])
         assert np.linalg.norm(x[2].ravel() - xs) <= bound * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("dt_frac", [0.2, 0.5, 0.9, 1.0])
+def test_A_3d_spectrum_spans_zero_to_eight_ninths(dt_frac):
+    """3D, cubic cells: the eigenvalues of the assembled A (all three
+    components coupled) fill [0, 8/9] on an even grid, at any dt; this is the
+    interval the 3D Chebyshev solve takes."""
+    cfg = ref.Config(ndim=3, shape=(4, 4, 4), dt=dt_frac / math.sqrt(3))
+    ev = np.linalg.eigvalsh(assemble_A(cfg, 7))
+    assert ev.min() > -1e-13
+    assert abs(ev.max() - 8 / 9) < 1e-13
+
+
+def test_chebyshev_3d_iterates_are_the_chebyshev_polynomials():
+    """3D (cubic cells): the oracle's recurrence after k sweeps equals the
+    Chebyshev error polynomial on [1/9, 1] applied to the initial error, and
+    with a tolerance it reaches the dense direct solve in well under half the
+    sweeps of Alg 1; non-cubic cells are refused."""
+    rng = np.random.default_rng(23)
+    shape = (4, 4, 4)
+    dt = 0.6 / math.sqrt(3)
+    b = [rng.normal(size=shape) for _ in range(3)]
+    bv = np.concatenate([q.ravel() for q in b])
+    M = assemble_A(ref.Config(ndim=3, shape=shape, dt=dt), 7)
+    for k in (1, 2, 5, 11):
+        x, st = ref.solve(ref.Config(ndim=3, shape=shape, dt=dt, sweeps=k, solver=1), b)
+        xv = np.concatenate([q.ravel() for q in x])
+        want = _cheb_polynomial_iterate(M, bv, k, 8 / 9)
+        assert np.abs(xv - want).max() < 1e-12 * np.abs(want).max(), k
+        assert st.sweeps[0] == k
+    direct = np.linalg.solve(np.eye(M.shape[0]) - M, bv)
+    counts = {}
+    for solver in (0, 1):
+        x, st = ref.solve(ref.Config(ndim=3, shape=shape, dt=dt, sweeps=600, tol=1e-12, solver=solver), b)
+        xv = np.concatenate([q.ravel() for q in x])
+        assert np.abs(xv - direct).max() < 1e-10 * np.abs(direct).max()
+        counts[solver] = st.sweeps[0]
+    assert counts[1] < 0.5 * counts[0], counts
+    with pytest.raises(ValueError):
+        ref.solve(ref.Config(ndim=3, shape=shape, dt=dt, d=(1.0, 1.0, 0.8), sweeps=3, solver=1), b)
