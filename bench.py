@@ -60,10 +60,10 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run 4 plain device copies of this many bytes (counter calibration)")
     ap.add_argument("--workload", default="modes2d",
-                    choices=["modes2d", "planewave_te", "planewave_3d", "batch", "adjoint", "chebyshev"],
+                    choices=["modes2d", "planewave_te", "planewave_3d", "batch", "adjoint", "chebyshev", "chebyshev_3d"],
                     help="modes2d (default): the 4096^2 line above; the others time the 128^2 TE "
                          "tolerance solve, the 512^3 3D solve, the 64-grid batch, the adjoint and the "
-                         "Chebyshev solve against Alg 1")
+                         "Chebyshev solve against Alg 1 in 2D (chebyshev) and 3D (chebyshev_3d)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -298,18 +298,17 @@ def bench_planewave_te(steps, warm):
                   "note": "latency bound: tiny kernels; the stop test runs on the device, one host read-back per step"})
 
 
-def bench_planewave_3d(steps, warm):
-    """512^3, FP32, all six components, tol 1e-7 (delta form)."""
+def _run_3d(steps, warm, solver, form):
+    """Step the 512^3 FP32 plane-wave workload (tol 1e-7) with one solver;
+    returns (Gcell-steps/s, details)."""
     import torch
     from paper_1907_13088_amd import inputs as I
     from paper_1907_13088_amd import mx
-    steps = steps or 5
-    warm = 1 if warm is None else warm
     t0 = time.time()
     w = I.planewave_3d(steps=steps + warm)
     log(f"3D inputs generated in {time.time() - t0:.1f}s")
     cfg = mx.make_config(3, w.shape[::-1], w.dt, w.d, "f32", 3, w.sweeps, w.tol, w.filter_passes,
-                         form=mx.FORM_DELTA)
+                         form=form, solver=solver)
     g = mx.Grid(cfg)
     E = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in w.E]
     B = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in w.B]
@@ -327,13 +326,35 @@ def bench_planewave_3d(steps, warm):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = g.profile_read()
+    g.close()
+    del E, B, J
+    torch.cuda.empty_cache()
     sw = prof["sweep"]
     sweeps = sum(s.sweeps[0] for s in st) / steps
-    return _line("512^3 plane wave + 32 pulses, FP32, tol 1e-7", w.cells * steps / dt / 1e9, "Gcell-steps/s",
-                 {"steps": steps, "ms_per_step": round(dt / steps * 1e3, 2), "mean_sweeps": round(sweeps, 1),
-                  "dtype": "f32", "nonconverged_steps": sum(s.nonconverged[0] for s in st),
-                  "sweep_pass_us": round(1e3 * sw["ms"] / max(sw["launches"], 1), 1),
-                  "sweep_pass_GBps": round(sw["bytes"] / (sw["ms"] / 1e3) / 1e9, 1) if sw["ms"] else None})
+    return w.cells * steps / dt / 1e9, {
+        "steps": steps, "ms_per_step": round(dt / steps * 1e3, 2), "mean_sweeps": round(sweeps, 1),
+        "nonconverged_steps": sum(s.nonconverged[0] for s in st),
+        "sweep_pass_us": round(1e3 * sw["ms"] / max(sw["launches"], 1), 1),
+        "sweep_pass_GBps": round(sw["bytes"] / (sw["ms"] / 1e3) / 1e9, 1) if sw["ms"] else None}
+
+
+def bench_planewave_3d(steps, warm):
+    """512^3, FP32, all six components, tol 1e-7 (delta form)."""
+    from paper_1907_13088_amd import mx
+    v, det = _run_3d(steps or 5, 1 if warm is None else warm, mx.SOLVER_ALG1, mx.FORM_DELTA)
+    return _line("512^3 plane wave + 32 pulses, FP32, tol 1e-7", v, "Gcell-steps/s", {**det, "dtype": "f32"})
+
+
+def bench_chebyshev_3d(steps, warm):
+    """The 512^3 FP32 workload to tol 1e-7 with the Chebyshev solve (cubic
+    cells, 1 - A on [1/9, 1], one sweep per pass), beside Alg 1 (delta form)."""
+    from paper_1907_13088_amd import mx
+    steps, warm = steps or 5, 1 if warm is None else warm
+    v1, d1 = _run_3d(steps, warm, mx.SOLVER_ALG1, mx.FORM_DELTA)
+    vc, dc = _run_3d(steps, warm, mx.SOLVER_CHEBYSHEV, mx.FORM_STANDARD)
+    return _line("512^3 plane wave + 32 pulses, FP32, tol 1e-7, Chebyshev solve", vc, "Gcell-steps/s",
+                 {"dtype": "f32", "chebyshev": dc, "alg1_delta": {**d1, "Gcell_steps_per_s": round(v1, 4)},
+                  "speedup": round(vc / v1, 3)})
 
 
 def bench_batch(steps, warm):
@@ -497,7 +518,8 @@ def bench_chebyshev(steps, warm):
 
 
 OTHER_WORKLOADS = {"planewave_te": bench_planewave_te, "planewave_3d": bench_planewave_3d,
-                   "batch": bench_batch, "adjoint": bench_adjoint, "chebyshev": bench_chebyshev}
+                   "batch": bench_batch, "adjoint": bench_adjoint, "chebyshev": bench_chebyshev,
+                   "chebyshev_3d": bench_chebyshev_3d}
 
 
 if __name__ == "__main__":

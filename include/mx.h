@@ -76,8 +76,9 @@ extern "C" {
    (Sec. 2.2.1).  It counts sweeps like Alg 1 (one application of A each)
    and its tolerance test uses the same residual ||dE' + A x - x||_2, but
    its iterates differ: it reaches a given residual in far fewer sweeps.
-   2D row streaming only (variants 0, 2, 3), standard form, not lumped; not
-   in a batch.  Its result after m sweeps is a polynomial in A applied to
+   2D row streaming (variants 0, 2, 3) or 3D with cubic cells (where 1 - A
+   spans [1/9, 1]) at one sweep per pass; standard form, not lumped; not in
+   a batch.  Its result after m sweeps is a polynomial in A applied to
    dE', so mx_adjoint transposes it with the same kernels. */
 #define MX_SOLVER_ALG1      0
 #define MX_SOLVER_CHEBYSHEV 1
@@ -116,9 +117,10 @@ typedef struct mx_config {
                              tolerance), 2 row streaming
                              (both blocks per pass), 3 row streaming (each block
                              on its own) */
-    int solver;           /* MX_SOLVER_ALG1 (default) or MX_SOLVER_CHEBYSHEV; the
-                             Chebyshev passes fuse at most: both blocks 5 (FP32),
-                             2 (FP64); TE 8, 3; TM 12, 6 */
+    int solver;           /* MX_SOLVER_ALG1 (default) or MX_SOLVER_CHEBYSHEV (2D,
+                             and 3D with cubic cells at one sweep per pass); the
+                             2D Chebyshev passes fuse at most: both blocks 5
+                             (FP32), 2 (FP64); TE 8, 3; TM 12, 6 */
 } mx_config;
 
 typedef struct mx_step_stats {

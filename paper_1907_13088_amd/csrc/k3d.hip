@@ -203,9 +203,14 @@ constexpr int ZX = 64, ZY = 8, ZT = ZX * ZY;
 constexpr int PX = ZX + 2, PY = ZY + 2, PCELLS = PX * PY;
 constexpr int PLOAD = (PCELLS + ZT - 1) / ZT;   // halo-tile cells per thread
 
-template <typename T, bool DELTA>
+// FORM: FM_STD (Alg 1), FM_DELTA, or FM_CHEB (the Chebyshev sweep: with
+// b + A x formed as in Alg 1, r = (b + A x) - x, d = f d_prev + g r and
+// x + d; the increment of the own cell passes in and out through s_in and
+// s_out, and f, g of this sweep are cheb[0][0][0], cheb[0][1][0]).
+template <typename T, int FORM>
 __global__ __launch_bounds__(ZT) void k3_sweep(Coef<T> c, SweepArgs<T> a, int flags, int Lz)
 {
+    constexpr bool DELTA = FORM == FM_DELTA, CHEB = FORM == FM_CHEB;
     if (a.skip && *a.skip) return;   // the solve has met its stop test
     __shared__ T pl[3][3][PY][PX];   // [slot][component][y][x]
     __shared__ double sred[2 * ZT / 64];
@@ -247,10 +252,14 @@ __global__ __launch_bounds__(ZT) void k3_sweep(Coef<T> c, SweepArgs<T> a, int fl
                 for (int q = 0; q < 3; q++) (&pl[slot][q][0][0])[hidx[u]] = pre[u][q];
     };
     const size_t own = (size_t)(out ? gy : 0) * nx + (out ? gx : 0);
-    T cnext[3] = {T(0), T(0), T(0)};
+    T cnext[3] = {T(0), T(0), T(0)}, dnext[3] = {T(0), T(0), T(0)};
     auto fetch_own = [&](int k) {
         if (!out || k >= Z1) return;
-        for (int q = 0; q < 3; q++) cnext[q] = cin[q][(size_t)k * plane + own];
+        for (int q = 0; q < 3; q++) {
+            cnext[q] = cin[q][(size_t)k * plane + own];
+            // no increment before the first sweep (its factor is 0)
+            if (CHEB) dnext[q] = first ? T(0) : a.s_in[q][(size_t)k * plane + own];
+        }
     };
 
     int sm = 0, s0 = 1, sp = 2;   // slots of planes k-1, k, k+1
@@ -264,6 +273,7 @@ __global__ __launch_bounds__(ZT) void k3_sweep(Coef<T> c, SweepArgs<T> a, int fl
     for (int k = Z0; k < Z1; k++) {
         deposit(sp);
         const T cown[3] = {cnext[0], cnext[1], cnext[2]};
+        const T down[3] = {dnext[0], dnext[1], dnext[2]};
         __syncthreads();
         if (k + 2 <= Z1) fetch(k + 2);
         fetch_own(k + 1);
@@ -277,16 +287,28 @@ __global__ __launch_bounds__(ZT) void k3_sweep(Coef<T> c, SweepArgs<T> a, int fl
             T ax, ay, az;
             apply_A3(c, at(0), at(1), at(2), ax, ay, az);
             const size_t o = (size_t)k * plane + own;
-            const T v[3] = {DELTA ? ax : cown[0] + ax, DELTA ? ay : cown[1] + ay, DELTA ? az : cown[2] + az};
+            T v[3] = {DELTA ? ax : cown[0] + ax, DELTA ? ay : cown[1] + ay, DELTA ? az : cown[2] + az};
+            T nd[3] = {T(0), T(0), T(0)}, rr[3] = {T(0), T(0), T(0)};
+            if (CHEB) {
+                const T f = a.cheb[0][0][0], gr = a.cheb[0][1][0];
+                for (int q = 0; q < 3; q++) {
+                    const T xo = pl[s0][q][ty + 1][tx + 1];
+                    rr[q] = v[q] - xo;
+                    nd[q] = fma(f, down[q], gr * rr[q]);
+                    v[q] = xo + nd[q];
+                }
+            }
             for (int q = 0; q < 3; q++) {
                 if (flags & SW_RESID) {
-                    const double d = DELTA ? (double)v[q] : (double)v[q] - (double)pl[s0][q][ty + 1][tx + 1];
+                    const double d = CHEB ? (double)rr[q]
+                                   : DELTA ? (double)v[q] : (double)v[q] - (double)pl[s0][q][ty + 1][tx + 1];
                     acc += d * d;
                 }
                 const T sum = DELTA ? cown[q] + v[q] : T(0);
                 if (flags & SW_STORE) {
                     a.x_out[q][o] = v[q];
                     if (DELTA) a.s_out[q][o] = sum;
+                    if (CHEB) a.s_out[q][o] = nd[q];
                 }
                 if (flags & SW_LAST) a.E[q][o] += DELTA ? sum : v[q];
             }
@@ -483,9 +505,11 @@ hipError_t launch_rhs3d(const Coef<T> &c, const T *const B[3], const T *const Jf
 }
 
 template <typename T>
-hipError_t launch_sweep3d(const Coef<T> &c, int k, bool delta, int flags, const SweepArgs<T> &a,
+hipError_t launch_sweep3d(const Coef<T> &c, int k, int form, int flags, const SweepArgs<T> &a,
                           hipStream_t s, int *nwg)
 {
+    const bool delta = form == FM_DELTA;
+    if (form == FM_CHEB && k != 1) return hipErrorInvalidValue;   // the Chebyshev form runs one sweep per pass
     if constexpr (sizeof(T) == 4) {
         if (k == 2) {
         // enough workgroups for whole rounds of one per CU, chunks of >= 16 planes
@@ -508,8 +532,9 @@ hipError_t launch_sweep3d(const Coef<T> &c, int k, bool delta, int flags, const 
     nzc = (c.nz + Lz - 1) / Lz;
     dim3 g(gx, gy, nzc);
     *nwg = g.x * g.y * g.z;
-    if (delta) hipLaunchKernelGGL((k3_sweep<T, true>), g, dim3(ZT), 0, s, c, a, flags, Lz);
-    else hipLaunchKernelGGL((k3_sweep<T, false>), g, dim3(ZT), 0, s, c, a, flags, Lz);
+    if (form == FM_CHEB) hipLaunchKernelGGL((k3_sweep<T, FM_CHEB>), g, dim3(ZT), 0, s, c, a, flags, Lz);
+    else if (delta) hipLaunchKernelGGL((k3_sweep<T, FM_DELTA>), g, dim3(ZT), 0, s, c, a, flags, Lz);
+    else hipLaunchKernelGGL((k3_sweep<T, FM_STD>), g, dim3(ZT), 0, s, c, a, flags, Lz);
     return hipGetLastError();
 }
 
@@ -519,7 +544,7 @@ hipError_t launch_sweep3d(const Coef<T> &c, int k, bool delta, int flags, const 
     template hipError_t launch_faraday3d<T>(const Coef<T> &, const T *const[3], T *const[3], hipStream_t); \
     template hipError_t launch_rhs3d<T>(const Coef<T> &, const T *const[3], const T *const[3], T,     \
                                         T *const[3], double *, hipStream_t, int *);                   \
-    template hipError_t launch_sweep3d<T>(const Coef<T> &, int, bool, int, const SweepArgs<T> &, hipStream_t, int *);
+    template hipError_t launch_sweep3d<T>(const Coef<T> &, int, int, int, const SweepArgs<T> &, hipStream_t, int *);
 INST(float)
 INST(double)
 #undef INST

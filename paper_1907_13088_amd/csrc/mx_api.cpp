@@ -111,10 +111,10 @@ int stream_workgroups(const mx_config *c, int variant, int ncu)
 int n_arrays(const mx_config *c)
 {
     // dE' (3), two iterate buffers (6), running sum (3), then
-    // 2D: a second B buffer (3), and for the Chebyshev solve a second
-    // increment buffer (3); 3D: filtered current and a filter temp (6)
+    // 2D: a second B buffer (3); 3D: filtered current and a filter temp
+    // (6); the Chebyshev solve adds a second increment buffer (3)
     if (c->ndim == 2) return c->solver == MX_SOLVER_CHEBYSHEV ? 18 : 15;
-    return 18;
+    return c->solver == MX_SOLVER_CHEBYSHEV ? 21 : 18;
 }
 
 }  // namespace
@@ -205,8 +205,10 @@ struct ProfScope {
 static void fill_cheb(const mx_config *c, int n, std::vector<double> out[2][2])
 {
     const double rx = c->dt * c->dt / (c->d[0] * c->d[0]), ry = c->dt * c->dt / (c->d[1] * c->d[1]);
-    const double rho[2] = {2.0 / 3.0, std::max({2.0 / 3.0 * (1.0 - rx), 2.0 / 3.0 * (1.0 - ry),
-                                                8.0 / 9.0 - 2.0 / 9.0 * (rx + ry)})};
+    // 2D: TE 2/3, TM the largest corner of its bilinear symbol; 3D (cubic
+    // cells, one block, index 0): 8/9 at any dt
+    const double rho[2] = {c->ndim == 3 ? 8.0 / 9.0 : 2.0 / 3.0,
+                           std::max({2.0 / 3.0 * (1.0 - rx), 2.0 / 3.0 * (1.0 - ry), 8.0 / 9.0 - 2.0 / 9.0 * (rx + ry)})};
     n = std::max(n, 1);
     for (int b = 0; b < 2; b++) {
         const double theta = 1.0 - rho[b] / 2.0, delta = rho[b] / 2.0, s1 = theta / delta;
@@ -305,7 +307,10 @@ int mx_validate(const mx_config *c, int *warn)
     if (c->form != MX_FORM_STANDARD && c->form != MX_FORM_DELTA) return fail(MX_EINVAL, "bad form");
     if (c->solver != MX_SOLVER_ALG1 && c->solver != MX_SOLVER_CHEBYSHEV) return fail(MX_EINVAL, "bad solver");
     if (c->solver == MX_SOLVER_CHEBYSHEV) {
-        if (c->ndim != 2) return fail(MX_EINVAL, "the Chebyshev solve is defined for 2D grids");
+        if (c->ndim == 3 && !(c->d[0] == c->d[1] && c->d[1] == c->d[2]))
+            return fail(MX_EINVAL, "the 3D Chebyshev solve is defined for cubic cells");
+        if (c->ndim == 3 && c->sweeps_per_pass > 1)
+            return fail(MX_EINVAL, "the 3D Chebyshev solve runs one sweep per pass");
         if (c->variant == 1) return fail(MX_EINVAL, "the Chebyshev solve runs on the row-streaming kernels (variant 0, 2 or 3)");
         if (c->form != MX_FORM_STANDARD) return fail(MX_EINVAL, "the Chebyshev solve uses the standard form");
         if (c->lumped) return fail(MX_EINVAL, "the lumped scheme has A = 0: no solve to accelerate");
@@ -401,6 +406,8 @@ int mx_init(const mx_config *cfg, void *stream, void *workspace, size_t workspac
         for (int q = 0; q < 3; q++) take(&g->Jf[q]);
         for (int q = 0; q < 3; q++) take(&g->Jt[q]);
         for (int q = 0; q < 3; q++) g->Bws[q] = nullptr;
+        if (cfg->solver == MX_SOLVER_CHEBYSHEV)
+            for (int q = 0; q < 3; q++) take(&g->D2[q]);
     }
     g->partial = (double *)p;
     p += up((size_t)max_wg(cfg) * 2 * sizeof(double));
@@ -648,7 +655,7 @@ int solve_tol(mx_grid *g, void *const rhs[3], const int *target_in, const T **re
                     else if (c.ndim == 2)
                         e = launch_stream2d<T>(k, 1 << b, kk, form, flags, a, g->stream, &nwg, 0);
                     else
-                        e = launch_sweep3d<T>(k, kk, delta, flags, a, g->stream, &nwg);
+                        e = launch_sweep3d<T>(k, kk, form, flags, a, g->stream, &nwg);
                 }
                 if (e != hipSuccess) return fail(MX_EDEVICE, "sweep launch: %s", hipGetErrorString(e));
                 {
@@ -763,7 +770,7 @@ int run_sweeps(mx_grid *g, void *const rhs[3], const int *target_in, bool tolmod
                              (double)g->ncell * sizeof(T) * pass_arrays(cheb, false, first, fin) * ncomp);
                 if (c.ndim == 2 && g->variant == 1) e = launch_sweep2d<T>(k, act, kk, false, flags, a, g->stream, &nwg);
                 else if (c.ndim == 2) e = launch_stream2d<T>(k, act, kk, form, flags, a, g->stream, &nwg, 0);
-                else e = launch_sweep3d<T>(k, kk, false, flags, a, g->stream, &nwg);
+                else e = launch_sweep3d<T>(k, kk, form, flags, a, g->stream, &nwg);
             }
             if (e != hipSuccess) return fail(MX_EDEVICE, "sweep launch: %s", hipGetErrorString(e));
             for (int b = 0; b < nblk; b++)

@@ -221,9 +221,10 @@ hipError_t launch_faraday3d(const Coef<T> &c, const T *const E[3], T *const B[3]
 template <typename T>
 hipError_t launch_rhs3d(const Coef<T> &c, const T *const B[3], const T *const Jf[3], T env_src,
                         T *const dEp[3], double *partial, hipStream_t s, int *nwg);
-// one pass of k sweeps (k = 1; k = 2 in FP32) over a 3D grid
+// one pass of k sweeps (k = 1; k = 2 in FP32, iterate forms FM_STD and
+// FM_DELTA) over a 3D grid, in iterate form `form`
 template <typename T>
-hipError_t launch_sweep3d(const Coef<T> &c, int k, bool delta, int flags, const SweepArgs<T> &a,
+hipError_t launch_sweep3d(const Coef<T> &c, int k, int form, int flags, const SweepArgs<T> &a,
                           hipStream_t s, int *nwg);
 
 // FP64 partial-sum reduction: out[0..1] = sum over nwg rows of partial[row][0..1]

@@ -28,7 +28,7 @@ EXPORTS = ["mx_profile_enable", "mx_profile_read", "mx_last_error", "mx_config_d
            "mx_bind_fields", "mx_set_current", "mx_step", "mx_get_step", "mx_set_step",
            "mx_get_sweeps_per_pass", "mx_get_block_sweeps_per_pass", "mx_destroy", "mx_adjoint", "mx_sources_assemble",
            "mx_sources_project", "mx_batch_workspace_size", "mx_batch_init", "mx_batch_bind",
-           "mx_batch_step", "mx_batch_get_plan", "mx_batch_destroy"]
+           "mx_batch_step", "mx_batch_get_plan", "mx_batch_get_schedule", "mx_batch_destroy"]
 
 
 class MxError(RuntimeError):

@@ -182,3 +182,37 @@ def test_3d_full_size_sampled_windows_in_bench_configuration():
         e = rel_err(got, [a[s0, s0, s0] for a in Eo + Bo])
         log(f"3D window at {c}, {m} sweeps: FP32 GPU vs FP64 oracle {max(e):.2e}")
         assert max(e) < 1e-5, (c, e)
+
+
+def test_3d_chebyshev_fixed_m_and_tolerance(small3d):
+    """The 3D Chebyshev solve (cubic cells, one sweep per pass): FP64 with a
+    fixed count within 1e-12 of the oracle's Chebyshev solve on a ragged box;
+    under a tolerance the GPU's counts agree with the oracle's (up to a tie),
+    need well under half the sweeps of Alg 1, and a replay of the oracle's
+    counts reproduces its fields; FP32 with a fixed count within 1e-5."""
+    import copy
+    CHEB = mx.SOLVER_CHEBYSHEV
+    w = _reshape(copy.deepcopy(small3d), (20, 22, 23))
+    Eg, Bg, _, _ = run_gpu(w, 4, sweeps=9, tol=0.0, solver=CHEB)
+    Eo, Bo, _ = run_oracle(w, 4, sweeps=9, tol=0.0, solver=CHEB)
+    e = rel_err(Eg + Bg, Eo + Bo)
+    log(f"3D chebyshev fixed m fp64 errors {max(e):.2e}")
+    assert max(e) < 1e-12
+    w = small3d
+    nsteps = 4
+    Eg, Bg, stg, spp = run_gpu(w, nsteps, tol=1e-9, solver=CHEB)
+    Eo, Bo, sto = run_oracle(w, nsteps, tol=1e-9, check_every=spp, solver=CHEB)
+    _, _, st1 = run_oracle(w, nsteps, tol=1e-9, check_every=spp)
+    log(f"3D chebyshev counts gpu {[s.sweeps[0] for s in stg]} oracle {[s.sweeps[0] for s in sto]} "
+        f"alg1 {[s.sweeps[0] for s in st1]}")
+    for a, b in zip(stg, sto):
+        assert abs(a.sweeps[0] - b.sweeps[0]) <= spp
+    assert sum(s.sweeps[0] for s in sto) < 0.5 * sum(s.sweeps[0] for s in st1)
+    Eg, Bg, _, _ = run_gpu(w, nsteps, replay=[s.sweeps for s in sto], solver=CHEB)
+    assert max(rel_err(Eg + Bg, Eo + Bo)) < 1e-12
+    w32 = _reshape(copy.deepcopy(small3d), (20, 22, 23))
+    Eg, Bg, _, _ = run_gpu(w32, 4, dtype="f32", sweeps=9, tol=0.0, solver=CHEB)
+    Eo, Bo, _ = run_oracle(w32, 4, sweeps=9, tol=0.0, solver=CHEB)
+    e = rel_err(Eg + Bg, Eo + Bo)
+    log(f"3D chebyshev fixed m fp32 errors {max(e):.2e}")
+    assert max(e) < 1e-5
