@@ -1,10 +1,14 @@
 """Seeded synthetic workloads for the finite-element Maxwell field step.
 
 This module only *draws* inputs: initial fields, prescribed current shapes,
-source envelopes and time steps.  It holds none of the solver's arithmetic
-(no discrete curl, no averaging operator, no mass-matrix sweep), so both the
-HIP path and the FP64 oracle can take their inputs from here without sharing
-any of the method's code.
+source envelopes and time steps.  It holds none of the step's arithmetic
+(no Faraday or Ampere update, no averaging operator, no mass-matrix sweep,
+no filter), so both the HIP path and the FP64 oracle can take their inputs
+from here without sharing any of the method's code.  Two input properties
+are built in from the grid alone: mode polarisations use the discrete
+wavenumber [k]_i = 2 sin(k_i d_i / 2) / d_i, and the current is the exact
+difference of a sampled potential, so that the initial fields and the
+current are divergence-free on the staggered grid (Appendix A).
 
 Conventions
 -----------
@@ -131,14 +135,22 @@ def draw_modes(rng: np.random.Generator, N: Sequence[int], count: int, kmax: flo
     return out
 
 
+def _kbracket(n_int: int, N: int, d: float = 1.0) -> float:
+    """Discrete wavenumber [k] = 2 sin(k d / 2) / d of lattice mode n on N cells:
+    a centred difference across one cell multiplies e^{ikx} by i [k]."""
+    return 2.0 * math.sin(math.pi * n_int / N) / d
+
+
 def em_wave_fields(shape: Tuple[int, ...], te_modes: Sequence[Mode], tm_modes: Sequence[Mode]):
-    """Continuum-transverse 2D plane waves: TE modes set (E_x, E_y, B_z) with
-    E = a (-k_y, k_x)/|k|, B_z = a; TM modes set (E_z, B_x, B_y) with
-    E_z = a, B = a (k_y, -k_x)/|k|.  Returns (E[3], B[3])."""
+    """Discretely transverse 2D plane waves: TE modes set (E_x, E_y, B_z) with
+    E = a (-[k]_y, [k]_x)/|[k]|, B_z = a; TM modes set (E_z, B_x, B_y) with
+    E_z = a, B = a ([k]_y, -[k]_x)/|[k]|.  With the discrete wavenumber the
+    staggered divergences of E and B vanish for every mode (up to rounding),
+    not only in the continuum limit.  Returns (E[3], B[3])."""
     assert len(shape) == 2
     ny, nx = shape
     def unit(md):
-        kx, ky = 2 * math.pi * md.n[0] / nx, 2 * math.pi * md.n[1] / ny
+        kx, ky = _kbracket(md.n[0], nx), _kbracket(md.n[1], ny)
         kk = math.hypot(kx, ky)
         return kx / kk, ky / kk
     te_u = [unit(m) for m in te_modes]
@@ -154,7 +166,7 @@ def em_wave_fields(shape: Tuple[int, ...], te_modes: Sequence[Mode], tm_modes: S
 
 
 # --------------------------------------------------------------------------
-# Prescribed currents: Gaussian pulses with a continuum-solenoidal TE part
+# Prescribed currents: Gaussian pulses, divergence-free on the staggered grid
 # --------------------------------------------------------------------------
 
 @dataclass
@@ -173,54 +185,62 @@ def _min_image(x: np.ndarray, c: float, n: int) -> np.ndarray:
 
 def pulse_current(shape: Tuple[int, ...], pulses: Sequence[Pulse], scale: float = 1.0 / FOUR_PI,
                   window: float = 6.0):
-    """J0 = sum of pulses (three components, positioned like E).
+    """J0 = sum of pulses (three components, positioned like E), divergence-free
+    on the staggered grid.
 
-    2D: psi = cos(phi) sigma g at each point, J_x = d psi/dy, J_y = -d psi/dx
-    (continuum derivatives, so the TE part is solenoidal in the continuum),
-    J_z = sin(phi) g.  3D: J = curl(p sigma g) = grad(sigma g) x p.
-    g = exp(-|x - c|^2 / 2 sigma^2) with periodic minimum image; each pulse is
-    evaluated in a window of +-window*sigma cells."""
+    Each pulse has a potential psi sampled at the B positions (one cell
+    corner per pair of axes): 2D psi = cos(phi) sigma g at B_z, and
+    J_x = psi(i+1/2, j+1/2) - psi(i+1/2, j-1/2), J_y = -(psi(i+1/2, j+1/2) -
+    psi(i-1/2, j+1/2)), J_z = sin(phi) g at E_z; 3D psi = p sigma g with
+    psi_x, psi_y, psi_z at B_x, B_y, B_z and J = the difference-curl of psi,
+    e.g. J_x = (psi_z(j+1/2) - psi_z(j-1/2)) - (psi_y(k+1/2) - psi_y(k-1/2)).
+    The staggered divergence of J then telescopes to zero at every node
+    (each psi sample enters it twice with opposite signs), so the charge
+    density the current transports stays constant (Appendix A).
+    g = exp(-|x - c|^2 / 2 sigma^2) with periodic minimum image; each pulse's
+    potential is evaluated in a window of +-window*sigma cells."""
     nd = len(shape)
     N = shape[::-1]
-    J = [np.zeros(shape) for _ in range(3)]
-    eo = E_OFFSETS[nd]
-    for p in pulses:
-        a = p.amp * scale
-        s = p.sigma
-        h = int(math.ceil(window * s))
-        for comp in range(3):
-            # index windows per axis (periodic)
+    bo = B_OFFSETS[nd]
+
+    def sampled(offset, weight_of):
+        """sum over pulses of weight_of(pulse) * amp * sigma-scaled g at one
+        staggered position (offset per axis), on the whole grid"""
+        out = np.zeros(shape)
+        for p in pulses:
+            w = weight_of(p)
+            if w == 0.0:
+                continue
+            s = p.sigma
+            h = int(math.ceil(window * s))
             idx, dist = [], []
             for ax in range(nd):
                 c = p.centre[ax]
-                base = int(math.floor(c - eo[comp][ax]))
-                if 2 * h + 2 < N[ax]:
-                    ii = np.arange(base - h, base + h + 2)
-                else:  # window wider than the grid: every cell once
-                    ii = np.arange(N[ax])
-                x = ii + eo[comp][ax]
-                dist.append(_min_image(x, c, N[ax]))
+                base = int(math.floor(c - offset[ax]))
+                ii = np.arange(base - h, base + h + 2) if 2 * h + 2 < N[ax] else np.arange(N[ax])
+                dist.append(_min_image(ii + offset[ax], c, N[ax]))
                 idx.append(np.mod(ii, N[ax]))
             if nd == 2:
                 dx, dy = np.meshgrid(dist[0], dist[1], indexing="xy")  # (ny, nx)
                 g = np.exp(-(dx * dx + dy * dy) / (2 * s * s))
-                if comp == 0:
-                    val = math.cos(p.phi) * s * g * (-dy / (s * s))
-                elif comp == 1:
-                    val = -math.cos(p.phi) * s * g * (-dx / (s * s))
-                else:
-                    val = math.sin(p.phi) * g
-                np.add.at(J[comp], np.ix_(idx[1], idx[0]), a * val)
+                np.add.at(out, np.ix_(idx[1], idx[0]), w * p.amp * scale * g)
             else:
                 dz, dy, dx = np.meshgrid(dist[2], dist[1], dist[0], indexing="ij")
                 g = np.exp(-(dx * dx + dy * dy + dz * dz) / (2 * s * s))
-                grad = (-dx / s * g, -dy / s * g, -dz / s * g)  # grad(sigma g)
-                px, py, pz = p.pol
-                cross = (grad[1] * pz - grad[2] * py,
-                         grad[2] * px - grad[0] * pz,
-                         grad[0] * py - grad[1] * px)
-                np.add.at(J[comp], np.ix_(idx[2], idx[1], idx[0]), a * cross[comp])
-    return J
+                np.add.at(out, np.ix_(idx[2], idx[1], idx[0]), w * p.amp * scale * g)
+        return out
+
+    def back(f, ax):
+        """f(x) - f(x - e_ax) along grid axis ax (0 = x), periodic"""
+        return f - np.roll(f, 1, axis=nd - 1 - ax)
+
+    if nd == 2:
+        psi = sampled(bo[2], lambda p: math.cos(p.phi) * p.sigma)
+        return [back(psi, 1), -back(psi, 0), sampled(E_OFFSETS[2][2], lambda p: math.sin(p.phi))]
+    psi = [sampled(bo[q], lambda p, q=q: p.pol[q] * p.sigma) for q in range(3)]
+    return [back(psi[2], 1) - back(psi[1], 2),
+            back(psi[0], 2) - back(psi[2], 0),
+            back(psi[1], 0) - back(psi[0], 1)]
 
 
 def draw_pulses(rng: np.random.Generator, N: Sequence[int], count: int, sigma: float = 8.0) -> List[Pulse]:
@@ -320,7 +340,9 @@ def modes_2d(n: Tuple[int, int] = (4096, 4096), courant: float = 0.5, nmodes: in
         env = envelope(steps, round_to(np.float32 if dtype == "f32" else np.float64, dt), omega)
     return _finish(Workload("modes_2d", 2, shape, (1.0, 1.0), dt, dtype, 3, m, 0.0,
                             filter_passes if npulses > 0 else 0, steps, E, B, J0, env,
-                            {"seed": seed, "courant": courant, "nmodes": nmodes, "npulses": npulses}))
+                            {"seed": seed, "courant": courant, "nmodes": nmodes, "npulses": npulses,
+                             "modes": [{"n": md.n, "amp": md.amp, "phase": md.phase, "pol": "TE" if t else "TM"}
+                                       for md, t in zip(modes, is_te)]}))
 
 
 def planewave_3d(n: int = 512, courant: float = 0.4, kidx: int = 16, noise: float = 1e-3,
