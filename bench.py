@@ -33,10 +33,18 @@ HBM_PEAK_GBS = 8000.0
 VALU_FP32_PEAK_TFLOPS = 78.6
 HERE = os.path.dirname(os.path.abspath(__file__))
 PROFILE_SUMMARY = os.path.join(HERE, "profiles", "sweep_pass_2d_4096sq_f32.md")
-# per-launch timing events are recorded on PSTEPS steps in PSTRIDE of the
-# timed region (even counts per call: the library then hands B back in the
-# caller's buffer without a copy at the end of each call)
-PSTRIDE, PSTEPS = 20, 2
+# per-launch timing events are recorded on the last steps of the timed
+# region: all of it below PSTRIDE steps, else an even count near K / 4 (the
+# event records cost about 3 us per launch; even step counts per call let
+# the library hand B back in the caller's buffer without a copy)
+PSTRIDE = 20
+# single steps after the timed region whose two probed lattice modes give
+# the fitted frequencies omega(k) of the FP32 and FP64 runs
+OMEGA_TAIL = 8
+
+
+def sampled_steps(K):
+    return K if K < PSTRIDE else max(2, (K // 4) & ~1)
 
 
 def log(msg):
@@ -103,9 +111,10 @@ def main():
     K, W = args.steps, args.warmup
     n = args.n
     t0 = time.time()
-    w = I.modes_2d((n, n), steps=W + K, dtype="f32")
+    w = I.modes_2d((n, n), steps=W + K + OMEGA_TAIL, dtype="f32")
     log(f"inputs generated in {time.time() - t0:.1f}s")
     env = [float(x) for x in w.env]
+    env_tail = env[W + K:]
     ncell = n * n
 
     def make(dtype):
@@ -120,51 +129,83 @@ def main():
         g.set_current(J)
         return g, E, B, J
 
+    # two probed lattice modes for the frequency fit: the largest amplitudes
+    # with |k| > 1, where the pulses' spectrum (sigma = 8) is negligible
+    import math
+    probes = sorted([md for md in w.meta["modes"]
+                     if math.hypot(*[2 * math.pi * md["n"][a] / n for a in range(2)]) > 1.0],
+                    key=lambda md: -abs(md["amp"]))[:2]
+
+    def project(F, md):
+        """(2/N) sum F exp(-i k.(x + offset)) in FP64 on the device"""
+        off = I.B_OFFSETS[2][2] if md["pol"] == "TE" else I.E_OFFSETS[2][2]
+        k = [2 * math.pi * md["n"][a] / n for a in range(2)]
+        ar = torch.arange(n, dtype=torch.float64, device=F.device)
+        ex, ey = torch.exp(-1j * k[0] * (ar + off[0])), torch.exp(-1j * k[1] * (ar + off[1]))
+        return complex(2.0 * (ey @ (F.double().to(torch.complex128) @ ex)) / F.numel())
+
+    def omega_fit(a, dt):
+        """w from a_{n+1} + a_{n-1} = 2 cos(w dt) a_n (least squares)"""
+        import numpy as np
+        a = np.asarray(a)
+        c = (np.vdot(a[1:-1], a[2:] + a[:-2]) / (2.0 * np.vdot(a[1:-1], a[1:-1]))).real
+        return math.acos(max(-1.0, min(1.0, c))) / dt
+
     def timed(dtype):
         g, E, B, J = make(dtype)
         g.step(W, env[:W])
         torch.cuda.synchronize()
-        # per-launch HIP events on the library stream, on every PSTRIDE-th
-        # step of the timed region (the event records themselves cost about
-        # 3 us per launch, so recording all of them would slow the run)
+        # per-launch HIP events on the library stream over the last ps steps
+        # of the timed region
+        ps = sampled_steps(K)
         g.profile_enable(True)
         g.profile_enable(False)
         s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         wall0 = time.perf_counter()
         s0.record()
-        nprof = 0
-        for c0 in range(0, K, PSTRIDE):
-            p = min(PSTEPS, K - c0)
-            g.profile_resume()
-            g.step(p, env[W + c0:W + c0 + p])
-            g.profile_enable(False)
-            nprof += p
-            rest = min(PSTRIDE, K - c0) - p
-            if rest > 0:
-                g.step(rest, env[W + c0 + p:W + c0 + p + rest])
+        if K > ps:
+            g.step(K - ps, env[W:W + K - ps])
+        g.profile_resume()
+        g.step(ps, env[W + K - ps:W + K])
+        g.profile_enable(False)
         s1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - wall0
         prof = g.profile_read()
         ms = s0.elapsed_time(s1)
         log(f"{dtype}: {K} steps in {ms:.1f} ms (wall {wall * 1e3:.1f} ms), "
-            f"sweeps per pass {g.block_sweeps_per_pass}")
-        return g, E, B, J, ms, prof, nprof
+            f"sweeps per pass {g.block_sweeps_per_pass}, events on the last {ps}")
+        state = [t.clone() for t in E + B]
+        # frequency probe: single steps after the timed region
+        ser = [[] for _ in probes]
+        for s in range(OMEGA_TAIL + 1):
+            for i, md in enumerate(probes):
+                ser[i].append(project(B[2] if md["pol"] == "TE" else E[2], md))
+            if s < OMEGA_TAIL:
+                g.step(1, [env_tail[s]])
+        omegas = [omega_fit(x, w.dt) for x in ser]
+        return g, state, ms, prof, ps, omegas
 
-    g32, E32, B32, J32, ms32, prof, nprof = timed("f32")
+    g32, st32, ms32, prof, nprof, om32 = timed("f32")
     value = ncell * K / (ms32 / 1e3) / 1e9
 
     fp64 = None
     if not args.no_fp64:
-        g64, E64, B64, J64, ms64, _, _ = timed("f64")
-        scale = max(float(t.abs().max()) for t in E64 + B64)
-        err = max(float((a.double() - b).abs().max()) for a, b in zip(E32 + B32, E64 + B64)) / scale
+        g64, st64, ms64, _, _, om64 = timed("f64")
+        scale = max(float(t.abs().max()) for t in st64)
+        err = max(float((a.double() - b).abs().max()) for a, b in zip(st32, st64)) / scale
+        om = [{"mode_n": list(md["n"]), "pol": md["pol"], "omega_fp32": a, "omega_fp64": b,
+               "rel_err": abs(a - b) / b} for md, a, b in zip(probes, om32, om64)]
         fp64 = {"value": round(ncell * K / (ms64 / 1e3) / 1e9, 3), "ms_per_step": round(ms64 / K, 5),
                 "fp32_vs_fp64_rel_err": err, "err_steps": W + K,
-                "err_metric": "max |FP32 - FP64| over the six components / max |FP64|"}
-        log(f"f64: {fp64['value']:.2f} Gcell-steps/s; FP32 vs FP64 normwise rel err after {W + K} steps: {err:.2e}")
+                "err_metric": "max |FP32 - FP64| over the six components / max |FP64|",
+                "omega": om, "omega_rel_err_max": max((x["rel_err"] for x in om), default=None),
+                "omega_metric": f"frequency of two lattice modes (|k| > 1, largest amplitudes) fitted from "
+                                f"their Fourier amplitudes over {OMEGA_TAIL} steps after the timed region"}
+        log(f"f64: {fp64['value']:.2f} Gcell-steps/s; FP32 vs FP64 normwise rel err after {W + K} steps: "
+            f"{err:.2e}; omega rel err {fp64['omega_rel_err_max']:.2e}")
         g64.close()
-        del E64, B64, J64
+        del st64
 
     total_ms = sum(v["ms"] for v in prof.values())
     kernels = {}
@@ -196,10 +237,16 @@ def main():
                 "kernel": f"k2_stream<float,3,K> row-streaming sweep passes storing their iterate "
                           f"(K = {'+'.join(map(str, store))}; final pass K = {depths[-1]} adds into E)",
                 "bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_s * 1e6, 2), "launches": nl,
-                "timed_launches": f"HIP events on every launch of {PSTEPS} steps in {PSTRIDE} of the timed region",
+                "timed_launches": f"HIP events on every launch of the last {nprof} of the {K} timed steps",
+                "limiter": "the 6- and 7-sweep passes are bound neither by HBM nor by VALU: each row step "
+                           "waits on an LDS neighbour exchange and barrier (measured against memory-only "
+                           "twins of the passes); shallower passes reach 56% of the HBM peak but take "
+                           "more passes per step",
                 "valu_tflops": round(flops_per_launch / avg_s / 1e12, 2) if avg_s > 0 else None,
                 "valu_peak_tflops": VALU_FP32_PEAK_TFLOPS,
-                "step_hbm_GBps": round(sum(v["bytes"] for v in prof.values()) / (total_ms / 1e3) / 1e9, 1)}
+                "step_hbm_GBps": round(sum(v["bytes"] for v in prof.values()) / (total_ms / 1e3) / 1e9, 1),
+                "sampled_kernel_us_per_step": round(1e3 * total_ms / max(nprof, 1), 2),
+                "kernel_sum_over_ms_per_step": round(total_ms / max(nprof, 1) / (ms32 / K), 4)}
 
     # bytes per cell-step: this schedule's (the per-launch algorithmic bytes of
     # every kernel category) against the unfused schedule (Faraday 9 words,
@@ -223,9 +270,27 @@ def main():
             ref.step(cfg, E, B, J0, env[steps])
             steps += 1
         ct = time.perf_counter() - c0
-        cpu = {"value": ncell * steps / ct / 1e9, "unit": "Gcell-steps/s", "cores": ref.num_threads(),
+        threads = ref.num_threads()
+        cpu = {"value": ncell * steps / ct / 1e9, "unit": "Gcell-steps/s", "cores": threads,
                "kind": "oracle",
                "sample": f"first {steps} steps of the same {n}x{n} workload, FP64 C oracle, {ct:.1f} s"}
+        # one thread, on a 1024^2 corner of the same fields and current (the
+        # oracle is a stencil code: its cell rate does not depend on the size
+        # once the arrays leave the caches)
+        c1 = min(n, 1024)
+        cut = lambda arrs: [a[:c1, :c1].copy() for a in arrs]
+        cfg1 = ref.Config(ndim=2, shape=(c1, c1), dt=w.dt, sweeps=w.sweeps, filter_passes=w.filter_passes)
+        E1, B1, J1 = cut(E), cut(B), cut(J0)
+        ref.set_num_threads(1)
+        try:
+            c0 = time.perf_counter()
+            for s in range(2):
+                ref.step(cfg1, E1, B1, J1, env[s])
+            ct1 = time.perf_counter() - c0
+        finally:
+            ref.set_num_threads(threads)
+        cpu["single_thread"] = {"value": c1 * c1 * 2 / ct1 / 1e9, "unit": "Gcell-steps/s", "cores": 1,
+                                "sample": f"2 steps on a {c1}x{c1} corner of the same workload, {ct1:.1f} s"}
         log(f"cpu oracle: {cpu}")
 
     out = {

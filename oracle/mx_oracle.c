@@ -550,3 +550,14 @@ int ora_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads the next parallel regions use (n >= 1); the CPU-baseline timing
+   runs the oracle on all host cores and on one. */
+void ora_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

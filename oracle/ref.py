@@ -60,6 +60,7 @@ def lib():
         L.ora_solve.argtypes = [C.POINTER(_Cfg), P3, P3, C.c_void_p, C.POINTER(_Stats)]
         L.ora_adjoint_step.argtypes = [C.POINTER(_Cfg), P3, P3, C.c_void_p, C.c_double, C.c_void_p]
         L.ora_num_threads.restype = C.c_int
+        L.ora_set_num_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -180,3 +181,8 @@ def adjoint_step(cfg: Config, Ebar, Bbar, J0bar, env: float, sweeps: Sequence[in
 
 def num_threads() -> int:
     return int(lib().ora_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (OpenMP)."""
+    lib().ora_set_num_threads(int(n))
