@@ -198,13 +198,22 @@ int persistent_steps(mx_batch *b, int nsteps, int bin0)
     persistent_shape(b->m, b->pk, &q, &npass, &nlow);
     const int nb = batch2d::persistent_blocks<T>(q);
     if (nb <= 0) return bfail(MX_EDEVICE, "no co-resident workgroups for the persistent batch kernel");
-    // barrier counters and error flag start at zero (a copy: no memset node
-    // in a captured stream)
+    // the barrier's arrival counter runs over a whole launch: at most
+    // 2^32 - 1 arrivals (npass + 1 barriers per step) per launch
+    const long long per_step = (long long)nb * (npass + 1);
+    const int max_steps = (int)std::min<long long>(0x7fffffffLL, 0xffffffffLL / per_step);
+    // barrier counters and error flag start at zero (copies: no memset node
+    // in a captured stream); a time-out flagged in one launch makes the
+    // later ones leave at their first barrier
     static const unsigned zero[4] = {0, 0, 0, 0};
-    BCHK(hipMemcpyAsync(b->bar, zero, 3 * sizeof(unsigned), hipMemcpyHostToDevice, b->stream));
     BCHK(hipMemcpyAsync(b->err, zero, sizeof(int), hipMemcpyHostToDevice, b->stream));
-    BCHK(batch2d::launch_persistent<T>((const GridDesc<T> *)b->desc, b->ng, b->items_f, b->items_s, b->pLf,
-                                       b->pLs, nsteps, q, npass, nlow, bin0, b->bar, b->err, nb, b->stream));
+    for (int s0 = 0; s0 < nsteps; s0 += max_steps) {
+        const int n = std::min(max_steps, nsteps - s0);
+        BCHK(hipMemcpyAsync(b->bar, zero, 3 * sizeof(unsigned), hipMemcpyHostToDevice, b->stream));
+        BCHK(batch2d::launch_persistent<T>((const GridDesc<T> *)b->desc, b->ng, b->items_f, b->items_s, b->pLf,
+                                           b->pLs, n, q, npass, nlow, bin0 ^ (s0 & 1), b->bar, b->err, nb,
+                                           b->stream));
+    }
     int h = 0;
     BCHK(hipMemcpyAsync(&h, b->err, sizeof(int), hipMemcpyDeviceToHost, b->stream));
     BCHK(hipStreamSynchronize(b->stream));
