@@ -110,11 +110,13 @@ int stream_workgroups(const mx_config *c, int variant, int ncu)
 // number of full-grid arrays in the workspace
 int n_arrays(const mx_config *c)
 {
-    // dE' (3), two iterate buffers (6), running sum (3), then
-    // 2D: a second B buffer (3); 3D: filtered current and a filter temp
-    // (6); the Chebyshev solve adds a second increment buffer (3)
+    // dE' (3), two iterate buffers (6), running sum (3), a second B buffer
+    // (3: the front writes B^{n+1/2} there, then the roles swap), then
+    // 3D: filtered current and a filter temp (6; the separate filter passes
+    // of p > 2 and the adjoint's current accumulator); the Chebyshev solve
+    // adds a second increment buffer (3)
     if (c->ndim == 2) return c->solver == MX_SOLVER_CHEBYSHEV ? 18 : 15;
-    return c->solver == MX_SOLVER_CHEBYSHEV ? 21 : 18;
+    return c->solver == MX_SOLVER_CHEBYSHEV ? 24 : 21;
 }
 
 }  // namespace
@@ -405,7 +407,7 @@ int mx_init(const mx_config *cfg, void *stream, void *workspace, size_t workspac
     } else {
         for (int q = 0; q < 3; q++) take(&g->Jf[q]);
         for (int q = 0; q < 3; q++) take(&g->Jt[q]);
-        for (int q = 0; q < 3; q++) g->Bws[q] = nullptr;
+        for (int q = 0; q < 3; q++) take(&g->Bws[q]);
         if (cfg->solver == MX_SOLVER_CHEBYSHEV)
             for (int q = 0; q < 3; q++) take(&g->D2[q]);
     }
@@ -831,6 +833,26 @@ int step_impl(mx_grid *g, int nsteps, const double *env, const int *replay, mx_s
             // B components of active blocks now live in the other buffer
             if (c.blocks & 1) g->bloc[2] ^= 1;
             if (c.blocks & 2) { g->bloc[0] ^= 1; g->bloc[1] ^= 1; }
+        } else if (c.filter_passes <= front3d_max_passes()) {
+            // one pass: Faraday into the other B buffer, filter, dE'
+            const T *Bin[3];
+            FrontArgs<T> a{};
+            for (int q = 0; q < 3; q++) {
+                Bin[q] = (const T *)(g->bloc[q] ? g->Bws[q] : g->B[q]);
+                a.B[q] = (T *)(g->bloc[q] ? g->B[q] : g->Bws[q]);
+                a.E[q] = (const T *)g->E[q];
+                a.J0[q] = g->has_j ? (const T *)g->J0[q] : nullptr;
+                a.dEp[q] = (T *)g->dEp[q];
+            }
+            a.env_src = env_src;
+            a.partial = tolmode ? g->partial : nullptr;
+            hipError_t er;
+            {
+                ProfScope ps(g, MX_PROF_FRONT, (double)g->ncell * sizeof(T) * (g->has_j ? 15 : 12));
+                er = launch_front3d<T>(k, c.filter_passes, a, Bin, g->stream, &nwg);
+            }
+            if (er != hipSuccess) return fail(MX_EDEVICE, "front launch: %s", hipGetErrorString(er));
+            for (int q = 0; q < 3; q++) g->bloc[q] ^= 1;
         } else {
             hipError_t er;
             {
@@ -892,14 +914,13 @@ int step_impl(mx_grid *g, int nsteps, const double *env, const int *replay, mx_s
         g->step++;
     }
     // hand the state back in the caller's B buffers
-    if (c.ndim == 2)
-        for (int q = 0; q < 3; q++)
-            if (g->bloc[q]) {
-                ProfScope ps(g, MX_PROF_OTHER, 2.0 * g->ncell * sizeof(T));
-                HIPCHK(hipMemcpyAsync(g->B[q], g->Bws[q], (size_t)g->ncell * sizeof(T), hipMemcpyDeviceToDevice,
-                                      g->stream));
-                g->bloc[q] = 0;
-            }
+    for (int q = 0; q < 3; q++)
+        if (g->bloc[q]) {
+            ProfScope ps(g, MX_PROF_OTHER, 2.0 * g->ncell * sizeof(T));
+            HIPCHK(hipMemcpyAsync(g->B[q], g->Bws[q], (size_t)g->ncell * sizeof(T), hipMemcpyDeviceToDevice,
+                                  g->stream));
+            g->bloc[q] = 0;
+        }
     return MX_OK;
 }
 

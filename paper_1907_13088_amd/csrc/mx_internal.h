@@ -212,6 +212,14 @@ int stream2d_kmax(bool f64, int block, int form);
 template <typename T>
 hipError_t launch_update(int64_t n, int comp_mask, T *const E[3], const T *const X[3], hipStream_t s);
 
+// Fused 3D front (k3f.hip): Faraday into a.B from Bin, p <= front3d_max_passes()
+// filter passes of the current, dE' (and its FP64 partial norms when
+// a.partial is set); *nwg receives the workgroup count
+int front3d_max_passes();
+template <typename T>
+hipError_t launch_front3d(const Coef<T> &c, int filter_passes, const FrontArgs<T> &a, const T *const Bin[3],
+                          hipStream_t s, int *nwg);
+
 // 3D launchers (k3d.hip)
 template <typename T>
 hipError_t launch_filter3d(const Coef<T> &c, int passes, const T *const J0[3], T *const Jf[3],

@@ -216,3 +216,47 @@ def test_3d_chebyshev_fixed_m_and_tolerance(small3d):
     e = rel_err(Eg + Bg, Eo + Bo)
     log(f"3D chebyshev fixed m fp32 errors {max(e):.2e}")
     assert max(e) < 1e-5
+
+
+def test_3d_chebyshev_fp32_tolerance_1e7():
+    """The 3D workload's recipe at 32^3 with the Chebyshev solve in FP32 at
+    tol 1e-7 (standard form: the residual b + A x - x is formed in FP32):
+    every step converges, the counts agree with the FP64 oracle's Chebyshev
+    solve up to one check, and with the oracle's counts replayed the fields
+    stay within 1e-5 of it."""
+    w = I.planewave_3d(n=32, kidx=1, npulses=4, sigma=3.0, filter_passes=1, tol=1e-7, m_max=300, steps=20,
+                       seed=3005, dtype="f32")
+    nsteps = 20
+    CHEB = mx.SOLVER_CHEBYSHEV
+    Eg, Bg, stg, spp = run_gpu(w, nsteps, solver=CHEB)
+    log(f"3D chebyshev fp32 tol 1e-7 counts {[s.sweeps[0] for s in stg]}, "
+        f"residuals {max(s.resid[0] / s.rhs[0] for s in stg):.2e}")
+    assert all(s.nonconverged[0] == 0 for s in stg)
+    Eo, Bo, sto = run_oracle(w, nsteps, check_every=spp, solver=CHEB)
+    for a, b in zip(stg, sto):
+        assert abs(a.sweeps[0] - b.sweeps[0]) <= spp
+    Eg, Bg, _, _ = run_gpu(w, nsteps, replay=[s.sweeps for s in sto], solver=CHEB)
+    e = rel_err(Eg + Bg, Eo + Bo)
+    log(f"3D chebyshev fp32 errors {max(e):.2e}")
+    assert max(e) < 1e-5
+
+
+@pytest.mark.parametrize("p,shape,with_j", [(0, (20, 22, 23), True), (1, (17, 40, 70), True),
+                                            (2, (20, 22, 23), True), (3, (12, 14, 18), True),
+                                            (1, (5, 3, 7), True), (1, (33, 9, 130), False)])
+def test_3d_front_filter_passes(p, shape, with_j):
+    """The 3D front (Faraday, p filter passes of the current, auxiliary
+    increment: one fused z-marching pass for p <= 2, separate kernels above)
+    on ragged boxes, some smaller than a workgroup tile in x, y or z, with and
+    without a current: FP64 within 1e-12 of the oracle over three steps."""
+    import copy
+    w = I.planewave_3d(n=72 if max(shape) <= 72 else 136, kidx=2, npulses=6, sigma=3.0, filter_passes=p,
+                       tol=0.0, m_max=3, steps=3, seed=3100 + p, dtype="f64")
+    w = _reshape(copy.deepcopy(w), shape)
+    if not with_j:
+        w.J0, w.env = None, None
+    Eg, Bg, _, _ = run_gpu(w, 3, sweeps=3, tol=0.0)
+    Eo, Bo, _ = run_oracle(w, 3, sweeps=3, tol=0.0)
+    e = rel_err(Eg + Bg, Eo + Bo)
+    log(f"3D front p={p} {shape} j={with_j}: {max(e):.2e}")
+    assert max(e) < 1e-12
