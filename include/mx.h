@@ -15,12 +15,14 @@
  *   5. E^{n+1} = E^n + dE
  * with c = 1, periodic boundaries in every axis.
  *
- * Memory model.  The caller owns every byte of device memory: field
+ * Memory model.  The caller owns the device memory of every grid: field
  * buffers are borrowed device pointers and the library's scratch lives in a
  * caller-provided workspace of mx_workspace_size() bytes.  The library never
- * allocates device memory (mx_init takes 80 bytes of pinned host memory, to
- * read the tolerance solve's state back).  All kernels run on the HIP stream
- * given to mx_init (NULL = the default stream).
+ * allocates device memory at run time (mx_init takes 80 bytes of pinned host
+ * memory, to read the tolerance solve's state back); its one static device
+ * array, the scratch of mx_step_static (MX_STATIC_SCRATCH_BYTES per GPU),
+ * comes with the loaded code.  All kernels run on the HIP stream given to
+ * mx_init (NULL = the default stream).
  *
  * Layout.  Each field component is one dense array in the grid dtype
  * (float or double), x fastest: index (k*ny + j)*nx + i, nz = 1 in 2D.
@@ -192,6 +194,33 @@ int mx_get_sweeps_per_pass(mx_grid *g, int *k);
 int mx_get_block_sweeps_per_pass(mx_grid *g, int k[2]);
 
 int mx_destroy(mx_grid *g);
+
+/* ------------------------------------------------------------------------
+ * Allocation-free stepping, for callers that cannot allocate memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  mx_step_static runs nsteps steps like mx_init + mx_bind_fields
+ * + mx_set_current + mx_step, with the same arguments and results, but its
+ * scratch (the workspace of mx_workspace_size) is a device array of
+ * MX_STATIC_SCRATCH_BYTES inside this library, one per GPU, held until the
+ * process ends: the call allocates no device or host memory and keeps no
+ * state between calls.  It runs on the current device, whose copy of the
+ * array it looks up on its first call there.
+ *   cfg      as for mx_init; Alg 1 only (MX_SOLVER_ALG1)
+ *   stream   hipStream_t (NULL = default stream)
+ *   E, B     the state (device pointers, grid layout), updated in place
+ *   J0       the current shape (device pointers) or NULL
+ *   nsteps, env, replay, stats   as for mx_step
+ * A config whose mx_workspace_size exceeds MX_STATIC_SCRATCH_BYTES is
+ * rejected with MX_EWORKSPACE before any device work (64 MiB hold, e.g., a
+ * 1024^2 FP32 or a 512 x 1024 FP64 2D grid).  Every call on one GPU uses the
+ * same array: calls that overlap on one GPU (other host threads, other
+ * streams) race and give wrong results; serialise them.  The array keeps
+ * the last call's contents; every value a step reads from it is written
+ * earlier in the same step, so nothing needs clearing between calls.
+ * ------------------------------------------------------------------------ */
+#define MX_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int mx_step_static(const mx_config *cfg, void *stream, void *const E[3], void *const B[3], void *const J0[3],
+                   int nsteps, const double *env, const int *replay, mx_step_stats *stats);
 
 /* ------------------------------------------------------------------------
  * Per-kernel timing.  While enabled, every launch of mx_step / mx_adjoint is

@@ -142,6 +142,7 @@ struct mx_grid {
     double *partial;      // device
     double *red;          // device, 2 doubles
     double *hred = nullptr;   // pinned host memory for read-backs (a TolState)
+    TolState hbuf;            // pageable read-back target when hred is not set
     TolState *tol;        // device: the tolerance solve's state within a step
     int spec[2] = {1, 1}; // passes per block the last tolerance solve ran (queued ahead next step)
     int spp[2];           // sweeps per pass of the TE and TM blocks (3D: [0])
@@ -265,6 +266,70 @@ static void fill_coef(const mx_config *c, Coef<T> &k)
     k.lumped = c->lumped;
 }
 
+// Lay a grid out on a validated config and a workspace of at least
+// mx_workspace_size bytes: the sweep-kernel choice, the arrays of the
+// workspace, the coefficients.  Allocates nothing (the caller sets hred, or
+// leaves it null for pageable read-backs into hbuf).
+static void grid_setup(mx_grid *g, const mx_config *cfg, hipStream_t stream, int device, char *ws, size_t ws_bytes)
+{
+    g->cfg = *cfg;
+    g->stream = stream;
+    g->device = device;
+    g->ws = ws;
+    g->ws_bytes = ws_bytes;
+    g->ncell = ncell_of(cfg);
+    g->step = 0;
+    g->bound = false;
+    g->has_j = false;
+    g->hred = nullptr;
+    // library choice: FP32 runs both blocks in one pass (7 sweeps deep);
+    // FP64, whose joint passes are only 3 deep, runs each block on its own
+    // (TE 5, TM 8 deep), which moves fewer bytes per step; so does the
+    // Chebyshev solve (joint passes 5 deep in FP32, per block 8 and 12:
+    // measured 0.46 against 0.60 ms per 4096^2 step at 7 sweeps).  A grid
+    // too small for the row-streaming passes to occupy half the CUs runs
+    // the LDS-tile kernel instead (128^2 to 768^2: 1.4 to 2.8 times faster
+    // per step; the Chebyshev solve has no tile form)
+    g->variant = cfg->variant > 0 ? cfg->variant
+                                  : (cfg->dtype == MX_F64 || cfg->solver == MX_SOLVER_CHEBYSHEV ? 3 : 2);
+    if (cfg->variant == 0 && cfg->ndim == 2 && cfg->solver != MX_SOLVER_CHEBYSHEV) {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cu < 1)
+            cu = 256;
+        if (stream_workgroups(cfg, g->variant, cu) < cu / 2) g->variant = 1;
+    }
+    pass_depths(cfg, g->variant, g->spp);
+    const size_t arr = up((size_t)g->ncell * elem_of(cfg));
+    char *p = g->ws;
+    auto take = [&](void **dst) { *dst = p; p += arr; };
+    for (int q = 0; q < 3; q++) take(&g->dEp[q]);
+    for (int b = 0; b < 2; b++)
+        for (int q = 0; q < 3; q++) take(&g->X[b][q]);
+    for (int q = 0; q < 3; q++) take(&g->S[q]);
+    for (int q = 0; q < 3; q++) g->D2[q] = nullptr;
+    if (cfg->ndim == 2) {
+        for (int q = 0; q < 3; q++) take(&g->Bws[q]);
+        for (int q = 0; q < 3; q++) g->Jf[q] = g->Jt[q] = nullptr;
+        if (cfg->solver == MX_SOLVER_CHEBYSHEV)
+            for (int q = 0; q < 3; q++) take(&g->D2[q]);
+    } else {
+        for (int q = 0; q < 3; q++) take(&g->Jf[q]);
+        for (int q = 0; q < 3; q++) take(&g->Jt[q]);
+        for (int q = 0; q < 3; q++) take(&g->Bws[q]);
+        if (cfg->solver == MX_SOLVER_CHEBYSHEV)
+            for (int q = 0; q < 3; q++) take(&g->D2[q]);
+    }
+    g->partial = (double *)p;
+    p += up((size_t)max_wg(cfg) * 2 * sizeof(double));
+    g->red = (double *)p;
+    p += up(8 * sizeof(double));
+    g->tol = (TolState *)p;
+    for (int q = 0; q < 3; q++) { g->E[q] = g->B[q] = g->J0[q] = nullptr; g->bloc[q] = 0; }
+    fill_coef(cfg, g->cf);
+    fill_coef(cfg, g->cd);
+    if (cfg->solver == MX_SOLVER_CHEBYSHEV) fill_cheb(cfg, cfg->sweeps, g->cheb);
+}
+
 extern "C" {
 
 const char *mx_last_error(void) { return g_err.c_str(); }
@@ -365,61 +430,7 @@ int mx_init(const mx_config *cfg, void *stream, void *workspace, size_t workspac
     HIPCHK(hipSetDevice(attr.device));
 
     mx_grid *g = new mx_grid();
-    g->cfg = *cfg;
-    g->stream = (hipStream_t)stream;
-    g->device = attr.device;
-    g->ws = (char *)workspace;
-    g->ws_bytes = workspace_bytes;
-    g->ncell = ncell_of(cfg);
-    g->step = 0;
-    g->bound = false;
-    g->has_j = false;
-    // library choice: FP32 runs both blocks in one pass (7 sweeps deep);
-    // FP64, whose joint passes are only 3 deep, runs each block on its own
-    // (TE 5, TM 8 deep), which moves fewer bytes per step; so does the
-    // Chebyshev solve (joint passes 5 deep in FP32, per block 8 and 12:
-    // measured 0.46 against 0.60 ms per 4096^2 step at 7 sweeps).  A grid
-    // too small for the row-streaming passes to occupy half the CUs runs
-    // the LDS-tile kernel instead (128^2 to 768^2: 1.4 to 2.8 times faster
-    // per step; the Chebyshev solve has no tile form)
-    g->variant = cfg->variant > 0 ? cfg->variant
-                                  : (cfg->dtype == MX_F64 || cfg->solver == MX_SOLVER_CHEBYSHEV ? 3 : 2);
-    if (cfg->variant == 0 && cfg->ndim == 2 && cfg->solver != MX_SOLVER_CHEBYSHEV) {
-        int cu = 0;
-        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, attr.device) != hipSuccess || cu < 1)
-            cu = 256;
-        if (stream_workgroups(cfg, g->variant, cu) < cu / 2) g->variant = 1;
-    }
-    pass_depths(cfg, g->variant, g->spp);
-    const size_t arr = up((size_t)g->ncell * elem_of(cfg));
-    char *p = g->ws;
-    auto take = [&](void **dst) { *dst = p; p += arr; };
-    for (int q = 0; q < 3; q++) take(&g->dEp[q]);
-    for (int b = 0; b < 2; b++)
-        for (int q = 0; q < 3; q++) take(&g->X[b][q]);
-    for (int q = 0; q < 3; q++) take(&g->S[q]);
-    for (int q = 0; q < 3; q++) g->D2[q] = nullptr;
-    if (cfg->ndim == 2) {
-        for (int q = 0; q < 3; q++) take(&g->Bws[q]);
-        for (int q = 0; q < 3; q++) g->Jf[q] = g->Jt[q] = nullptr;
-        if (cfg->solver == MX_SOLVER_CHEBYSHEV)
-            for (int q = 0; q < 3; q++) take(&g->D2[q]);
-    } else {
-        for (int q = 0; q < 3; q++) take(&g->Jf[q]);
-        for (int q = 0; q < 3; q++) take(&g->Jt[q]);
-        for (int q = 0; q < 3; q++) take(&g->Bws[q]);
-        if (cfg->solver == MX_SOLVER_CHEBYSHEV)
-            for (int q = 0; q < 3; q++) take(&g->D2[q]);
-    }
-    g->partial = (double *)p;
-    p += up((size_t)max_wg(cfg) * 2 * sizeof(double));
-    g->red = (double *)p;
-    p += up(8 * sizeof(double));
-    g->tol = (TolState *)p;
-    for (int q = 0; q < 3; q++) { g->E[q] = g->B[q] = g->J0[q] = nullptr; g->bloc[q] = 0; }
-    fill_coef(cfg, g->cf);
-    fill_coef(cfg, g->cd);
-    if (cfg->solver == MX_SOLVER_CHEBYSHEV) fill_cheb(cfg, cfg->sweeps, g->cheb);
+    grid_setup(g, cfg, (hipStream_t)stream, attr.device, (char *)workspace, workspace_bytes);
     // pinned host memory: the tolerance solve reads its state back by DMA
     // rather than through a staged pageable copy
     if (hipHostMalloc((void **)&g->hred, sizeof(TolState), hipHostMallocDefault) != hipSuccess) {
@@ -613,7 +624,7 @@ int solve_tol(mx_grid *g, void *const rhs[3], const int *target_in, const T **re
     }
     if (cheb && (int)g->cheb[0][0].size() < std::max(target[0], target[1]))
         fill_cheb(&c, std::max(target[0], target[1]), g->cheb);
-    TolState *hs = (TolState *)g->hred;
+    TolState *hs = g->hred ? (TolState *)g->hred : &g->hbuf;
     bool have = false;
     auto read_back = [&]() -> int {
         HIPCHK(hipMemcpyAsync(hs, g->tol, sizeof(TolState), hipMemcpyDeviceToHost, g->stream));
@@ -988,6 +999,49 @@ int mx_step(mx_grid *g, int nsteps, const double *env, const int *replay, mx_ste
     return g->cfg.dtype == MX_F64 ? step_impl<double>(g, nsteps, env, replay, stats)
                                   : step_impl<float>(g, nsteps, env, replay, stats);
 }
+
+}  // extern "C"
+
+namespace mx {
+// nsteps steps of a grid laid out on the scratch `ws` (ws_bytes) of the
+// current device, fields and current bound for this call only; allocates
+// nothing: the grid descriptor lives on the stack, the tolerance read-back
+// goes to pageable host memory, no timing events.  Alg 1 only (the
+// Chebyshev factors are kept in host vectors).
+int step_on_scratch(const mx_config *cfg, void *stream, int device, void *ws, size_t ws_bytes, void *const E[3],
+                    void *const B[3], void *const J0[3], int nsteps, const double *env, const int *replay,
+                    mx_step_stats *stats)
+{
+    int rc = mx_validate(cfg, nullptr);
+    if (rc) return rc;
+    if (cfg->solver != MX_SOLVER_ALG1)
+        return fail(MX_EINVAL, "the static-scratch step runs Alg 1 only (the Chebyshev factors need host memory)");
+    if (!E || !B) return fail(MX_EINVAL, "NULL argument");
+    for (int q = 0; q < 3; q++) {
+        if (!E[q] || !B[q]) return fail(MX_EINVAL, "field component %d is NULL", q);
+        if (J0 && !J0[q]) return fail(MX_EINVAL, "J0 component %d is NULL", q);
+    }
+    if (nsteps < 0) return fail(MX_EINVAL, "nsteps must be >= 0");
+    size_t need = 0;
+    mx_workspace_size(cfg, &need);
+    if (need > ws_bytes)
+        return fail(MX_EWORKSPACE, "this grid needs %zu bytes of scratch; the static scratch holds %zu", need,
+                    ws_bytes);
+    mx_grid g;
+    grid_setup(&g, cfg, (hipStream_t)stream, device, (char *)ws, ws_bytes);
+    for (int q = 0; q < 3; q++) {
+        g.E[q] = E[q];
+        g.B[q] = B[q];
+        g.J0[q] = J0 ? J0[q] : nullptr;
+    }
+    g.bound = true;
+    g.has_j = J0 != nullptr;
+    return cfg->dtype == MX_F64 ? step_impl<double>(&g, nsteps, env, replay, stats)
+                                : step_impl<float>(&g, nsteps, env, replay, stats);
+}
+}  // namespace mx
+
+extern "C" {
 
 int mx_adjoint(mx_grid *g, int nsteps, const double *env, const int *sweeps, void *const Ebar[3],
                void *const Bbar[3], void *const dJ0[3])

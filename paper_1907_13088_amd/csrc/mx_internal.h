@@ -212,6 +212,12 @@ int stream2d_kmax(bool f64, int block, int form);
 template <typename T>
 hipError_t launch_update(int64_t n, int comp_mask, T *const E[3], const T *const X[3], hipStream_t s);
 
+// mx_step on the scratch `ws` (ws_bytes) of device `device`, which is
+// current: the body of mx_step_static (mx_api.cpp)
+int step_on_scratch(const mx_config *cfg, void *stream, int device, void *ws, size_t ws_bytes, void *const E[3],
+                    void *const B[3], void *const J0[3], int nsteps, const double *env, const int *replay,
+                    mx_step_stats *stats);
+
 // Fused 3D front (k3f.hip): Faraday into a.B from Bin, p <= front3d_max_passes()
 // filter passes of the current, dE' (and its FP64 partial norms when
 // a.partial is set); *nwg receives the workgroup count

@@ -28,7 +28,9 @@ EXPORTS = ["mx_profile_enable", "mx_profile_read", "mx_last_error", "mx_config_d
            "mx_bind_fields", "mx_set_current", "mx_step", "mx_get_step", "mx_set_step",
            "mx_get_sweeps_per_pass", "mx_get_block_sweeps_per_pass", "mx_destroy", "mx_adjoint", "mx_sources_assemble",
            "mx_sources_project", "mx_batch_workspace_size", "mx_batch_init", "mx_batch_bind",
-           "mx_batch_step", "mx_batch_get_plan", "mx_batch_get_schedule", "mx_batch_destroy"]
+           "mx_batch_step", "mx_batch_get_plan", "mx_batch_get_schedule", "mx_batch_destroy",
+           "mx_step_static"]
+STATIC_SCRATCH_BYTES = 64 << 20   # MX_STATIC_SCRATCH_BYTES
 
 
 class MxError(RuntimeError):
@@ -92,6 +94,8 @@ def lib():
         L.mx_adjoint.argtypes = [vp, C.c_int, P(C.c_double), P(C.c_int), P(vp), P(vp), P(vp)]
         L.mx_sources_assemble.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, P(vp)]
         L.mx_sources_project.argtypes = [vp, C.c_int, C.c_int, vp, vp, P(vp), vp]
+        L.mx_step_static.argtypes = [P(CConfig), vp, P(vp), P(vp), P(vp), C.c_int, P(C.c_double), P(C.c_int),
+                                     P(CStats)]
         if hasattr(L, "mx_batch_init"):
             L.mx_batch_workspace_size.argtypes = [P(CConfig), C.c_int, P(C.c_size_t)]
             L.mx_batch_init.argtypes = [P(CConfig), C.c_int, vp, vp, C.c_size_t, P(vp)]
@@ -170,6 +174,44 @@ class Stats:
     nonconverged: tuple
 
 
+def _step_args(nsteps, env, replay, stats):
+    envp = None
+    if env is not None:
+        assert len(env) >= nsteps
+        envp = (C.c_double * max(nsteps, 1))(*[float(x) for x in env[:nsteps]])
+    rp = None
+    if replay is not None:
+        flat = []
+        for s in range(nsteps):
+            flat += [int(replay[s][0]), int(replay[s][1])]
+        rp = (C.c_int * max(2 * nsteps, 1))(*flat)
+    st = (CStats * max(nsteps, 1))() if stats else None
+    return envp, rp, st
+
+
+def _stats_list(st, nsteps):
+    return [Stats(tuple(x.sweeps), tuple(x.resid), tuple(x.rhs), tuple(x.nonconverged)) for x in st[:nsteps]]
+
+
+def step_static(cfg: CConfig, E: Sequence, B: Sequence, J0: Optional[Sequence] = None, nsteps: int = 1,
+                env: Optional[Sequence[float]] = None, replay: Optional[Sequence[Sequence[int]]] = None,
+                stats: bool = False, stream=None) -> Optional[List["Stats"]]:
+    """mx_step_static: nsteps steps of (E, B) in place on the library's static
+    device scratch (no allocation; configs up to STATIC_SCRATCH_BYTES of
+    workspace), on the current device and the given (default: current) stream."""
+    import torch
+    validate(cfg)
+    td = torch.float64 if cfg.dtype == MX_F64 else torch.float32
+    for t in list(E) + list(B) + (list(J0) if J0 is not None else []):
+        if t.dtype != td or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"fields must be contiguous {td} CUDA tensors")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    envp, rp, st = _step_args(nsteps, env, replay, stats)
+    _check(lib().mx_step_static(C.byref(cfg), C.c_void_p(s.cuda_stream), _ptrs(E), _ptrs(B),
+                                _ptrs(J0) if J0 is not None else None, nsteps, envp, rp, st))
+    return _stats_list(st, nsteps) if stats else None
+
+
 class Grid:
     """One periodic grid and its bound state (torch tensors on the GPU)."""
 
@@ -217,21 +259,9 @@ class Grid:
 
     def step(self, nsteps: int, env: Optional[Sequence[float]] = None,
              replay: Optional[Sequence[Sequence[int]]] = None, stats: bool = False) -> Optional[List[Stats]]:
-        envp = None
-        if env is not None:
-            assert len(env) >= nsteps
-            envp = (C.c_double * nsteps)(*[float(x) for x in env[:nsteps]])
-        rp = None
-        if replay is not None:
-            flat = []
-            for s in range(nsteps):
-                flat += [int(replay[s][0]), int(replay[s][1])]
-            rp = (C.c_int * (2 * nsteps))(*flat)
-        st = (CStats * nsteps)() if stats else None
+        envp, rp, st = _step_args(nsteps, env, replay, stats)
         _check(lib().mx_step(self.h, nsteps, envp, rp, st))
-        if not stats:
-            return None
-        return [Stats(tuple(x.sweeps), tuple(x.resid), tuple(x.rhs), tuple(x.nonconverged)) for x in st]
+        return _stats_list(st, nsteps) if stats else None
 
     def adjoint(self, nsteps: int, env: Optional[Sequence[float]], sweeps: Sequence[Sequence[int]],
                 Ebar: Sequence, Bbar: Sequence, dJ0: Optional[Sequence] = None):
