@@ -561,3 +561,163 @@ void ora_set_num_threads(int n)
     (void)n;
 #endif
 }
+
+/* ------------------------------------------------------------------------
+ * Particle coupling in 2D with three velocity components.  The paper runs
+ * the field solver inside a particle-in-cell code and keeps that code's
+ * force interpolation, current deposition and particle push (Sec. 2: only
+ * Faraday's and Ampere's equations change); Gauss's law for E then holds
+ * because the deposition conserves charge (Sec. 2, Appendix A).  The
+ * particle side is written here from the published methods it names:
+ *   push ........ the relativistic Boris scheme (Boris 1970; the push of
+ *                 the paper's experiments, Sec. 5): half electric kick,
+ *                 magnetic rotation, half electric kick, then the move
+ *   shapes ...... first-order B-spline (linear weighting) at each field
+ *                 component's staggered position, the lowest order of the
+ *                 paper's Table 1, the same shape for interpolation and
+ *                 deposition
+ *   deposition .. Esirkepov's charge-conserving density decomposition
+ *                 (Esirkepov 2001) in its 2D form with an out-of-plane
+ *                 current, so rho^{n+1} - rho^n + dt D.J^{n+1/2} = 0 holds
+ *                 exactly on the nodes
+ * Time levels: positions at n, momenta u = gamma v at n - 1/2 (c = 1); the
+ * force uses E^n and B^n = (B^{n-1/2} + B^{n+1/2})/2 = B^{n-1/2} - (dt/2)
+ * curl E^n; the move gives positions at n + 1 and the current J^{n+1/2}
+ * that the field step then uses (env = 1).  Positions are physical
+ * coordinates with node (i, j) at (i dx, j dy), kept in [0, L) by periodic
+ * wrapping.  rho and J are densities per cell area: a macro-particle of
+ * charge q and weight w carries charge q w.
+ * ------------------------------------------------------------------------ */
+
+/* linear B-spline */
+static double shape1(double d)
+{
+    d = fabs(d);
+    return d < 1.0 ? 1.0 - d : 0.0;
+}
+
+/* F at (x, y) interpolated with the linear shape; F sits at (i + ox, j + oy) cells */
+static double gather1(const ora_cfg *c, const double *F, double x, double y, double ox, double oy)
+{
+    const double xi = x / c->dx - ox, eta = y / c->dy - oy;
+    const long i0 = (long)floor(xi), j0 = (long)floor(eta);
+    double v = 0.0;
+    for (int b = 0; b < 2; b++)
+        for (int a = 0; a < 2; a++) {
+            const double wgt = shape1(xi - (double)(i0 + a)) * shape1(eta - (double)(j0 + b));
+            v += wgt * F[IDX(c, i0 + a, j0 + b, 0)];
+        }
+    return v;
+}
+
+static double wrap_pos(double x, double L)
+{
+    if (x >= L) return x - L;
+    if (x < 0.0) return x + L;
+    return x;
+}
+
+/* push np particles of charge q, mass m and weight w through one step and
+   add their current J^{n+1/2} into J; returns 1 if a particle would cross
+   more than one cell (the deposition stencil assumes |v| dt < cell), else 0 */
+int ora_pic_push_deposit(const ora_cfg *c, double *const E[3], double *const B[3], long np, double q, double m,
+                         double w, double *x, double *y, double *ux, double *uy, double *uz, double *const J[3])
+{
+    const long n = ncell(c);
+    const double dt = c->dt;
+    const double Lx = c->nx * c->dx, Ly = c->ny * c->dy;
+    /* B^n: half a Faraday step from B^{n-1/2} with E^n */
+    double *Bn[3];
+    for (int q3 = 0; q3 < 3; q3++) {
+        Bn[q3] = (double *)malloc(sizeof(double) * n);
+        memcpy(Bn[q3], B[q3], sizeof(double) * n);
+    }
+    ora_cfg half = *c;
+    half.dt = 0.5 * dt;
+    ora_faraday(&half, E, Bn);
+    const double h = q * dt / (2.0 * m);
+    const double cx = -q * w / (c->dy * dt), cy = -q * w / (c->dx * dt), cz = q * w / (c->dx * c->dy);
+    int bad = 0;
+    for (long p = 0; p < np; p++) {
+        const double x0 = x[p], y0 = y[p];
+        /* field at the particle (staggered positions of Sec. 2) */
+        const double ex = gather1(c, E[0], x0, y0, 0.5, 0.0);
+        const double ey = gather1(c, E[1], x0, y0, 0.0, 0.5);
+        const double ez = gather1(c, E[2], x0, y0, 0.0, 0.0);
+        const double bx = gather1(c, Bn[0], x0, y0, 0.0, 0.5);
+        const double by = gather1(c, Bn[1], x0, y0, 0.5, 0.0);
+        const double bz = gather1(c, Bn[2], x0, y0, 0.5, 0.5);
+        /* Boris: u- = u + h E; rotate about B by the angle of t = h B / gamma-;
+           u+ = u- + (u- + u- x t) x s, s = 2 t / (1 + t.t); u = u+ + h E */
+        const double umx = ux[p] + h * ex, umy = uy[p] + h * ey, umz = uz[p] + h * ez;
+        const double gm = sqrt(1.0 + umx * umx + umy * umy + umz * umz);
+        const double tx = h * bx / gm, ty = h * by / gm, tz = h * bz / gm;
+        const double upx = umx + (umy * tz - umz * ty);
+        const double upy = umy + (umz * tx - umx * tz);
+        const double upz = umz + (umx * ty - umy * tx);
+        const double f = 2.0 / (1.0 + tx * tx + ty * ty + tz * tz);
+        const double sx = f * tx, sy = f * ty, sz = f * tz;
+        const double uplx = umx + (upy * sz - upz * sy);
+        const double uply = umy + (upz * sx - upx * sz);
+        const double uplz = umz + (upx * sy - upy * sx);
+        const double nux = uplx + h * ex, nuy = uply + h * ey, nuz = uplz + h * ez;
+        const double g = sqrt(1.0 + nux * nux + nuy * nuy + nuz * nuz);
+        const double x1 = x0 + dt * nux / g, y1 = y0 + dt * nuy / g;
+        /* Esirkepov: local 4 x 4 node window starting one node left of the
+           particle's start cell */
+        const double xi0 = x0 / c->dx, eta0 = y0 / c->dy, xi1 = x1 / c->dx, eta1 = y1 / c->dy;
+        if (fabs(xi1 - xi0) >= 1.0 || fabs(eta1 - eta0) >= 1.0) bad = 1;
+        const long i0 = (long)floor(xi0) - 1, j0 = (long)floor(eta0) - 1;
+        double sx0[4], sx1[4], sy0[4], sy1[4];
+        for (int k = 0; k < 4; k++) {
+            sx0[k] = shape1(xi0 - (double)(i0 + k));
+            sx1[k] = shape1(xi1 - (double)(i0 + k));
+            sy0[k] = shape1(eta0 - (double)(j0 + k));
+            sy1[k] = shape1(eta1 - (double)(j0 + k));
+        }
+        const double vz = nuz / g;
+        for (int l = 0; l < 4; l++) {
+            double run = 0.0;   /* sum over k' <= k of W_x(k', l) */
+            for (int k = 0; k < 4; k++) {
+                const double wx = 0.5 * (sx1[k] - sx0[k]) * (sy0[l] + sy1[l]);
+                run += wx;
+                if (k < 3) J[0][IDX(c, i0 + k, j0 + l, 0)] += cx * run;
+            }
+        }
+        for (int k = 0; k < 4; k++) {
+            double run = 0.0;   /* sum over l' <= l of W_y(k, l') */
+            for (int l = 0; l < 4; l++) {
+                const double wy = 0.5 * (sy1[l] - sy0[l]) * (sx0[k] + sx1[k]);
+                run += wy;
+                if (l < 3) J[1][IDX(c, i0 + k, j0 + l, 0)] += cy * run;
+            }
+        }
+        for (int l = 0; l < 4; l++)
+            for (int k = 0; k < 4; k++) {
+                const double wz = (2.0 * sx0[k] * sy0[l] + sx1[k] * sy0[l] + sx0[k] * sy1[l] + 2.0 * sx1[k] * sy1[l]) / 6.0;
+                J[2][IDX(c, i0 + k, j0 + l, 0)] += cz * vz * wz;
+            }
+        x[p] = wrap_pos(x1, Lx);
+        y[p] = wrap_pos(y1, Ly);
+        ux[p] = nux;
+        uy[p] = nuy;
+        uz[p] = nuz;
+    }
+    for (int q3 = 0; q3 < 3; q3++) free(Bn[q3]);
+    return bad;
+}
+
+/* rho at the nodes (i, j) += q w / (dx dy) S(x/dx - i) S(y/dy - j) */
+void ora_pic_deposit_charge(const ora_cfg *c, long np, double q, double w, const double *x, const double *y,
+                            double *rho)
+{
+    const double cq = q * w / (c->dx * c->dy);
+    for (long p = 0; p < np; p++) {
+        const double xi = x[p] / c->dx, eta = y[p] / c->dy;
+        const long i0 = (long)floor(xi), j0 = (long)floor(eta);
+        for (int b = 0; b < 2; b++)
+            for (int a = 0; a < 2; a++)
+                rho[IDX(c, i0 + a, j0 + b, 0)] +=
+                    cq * shape1(xi - (double)(i0 + a)) * shape1(eta - (double)(j0 + b));
+    }
+}

@@ -61,6 +61,11 @@ def lib():
         L.ora_adjoint_step.argtypes = [C.POINTER(_Cfg), P3, P3, C.c_void_p, C.c_double, C.c_void_p]
         L.ora_num_threads.restype = C.c_int
         L.ora_set_num_threads.argtypes = [C.c_int]
+        PD = C.POINTER(C.c_double)
+        L.ora_pic_push_deposit.argtypes = [C.POINTER(_Cfg), P3, P3, C.c_long, C.c_double, C.c_double, C.c_double,
+                                           PD, PD, PD, PD, PD, P3]
+        L.ora_pic_push_deposit.restype = C.c_int
+        L.ora_pic_deposit_charge.argtypes = [C.POINTER(_Cfg), C.c_long, C.c_double, C.c_double, PD, PD, PD]
         _lib = L
     return _lib
 
@@ -186,3 +191,24 @@ def num_threads() -> int:
 def set_num_threads(n: int) -> None:
     """Threads of the oracle's parallel loops from now on (OpenMP)."""
     lib().ora_set_num_threads(int(n))
+
+
+def _pd(a):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def pic_push_deposit(cfg: Config, E, B, q: float, m: float, w: float, x, y, ux, uy, uz, J) -> None:
+    """One relativistic Boris push of a 2D species (positions x, y at n,
+    momenta u = gamma v at n - 1/2, updated in place) in E^n and
+    B^n = B^{n-1/2} - (dt/2) curl E^n, with its charge-conserving current
+    J^{n+1/2} added into J (three arrays placed like E)."""
+    bad = lib().ora_pic_push_deposit(C.byref(cfg.c()), _p3(E), _p3(B), len(x), q, m, w, _pd(x), _pd(y), _pd(ux),
+                                     _pd(uy), _pd(uz), _p3(J))
+    if bad:
+        raise ValueError("a particle moved a cell or more in one step")
+
+
+def pic_deposit_charge(cfg: Config, q: float, w: float, x, y, rho) -> None:
+    """rho at the nodes += the species' charge density (linear shapes)."""
+    lib().ora_pic_deposit_charge(C.byref(cfg.c()), len(x), q, w, _pd(x), _pd(y), _pd(rho))
