@@ -68,7 +68,8 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run 4 plain device copies of this many bytes (counter calibration)")
     ap.add_argument("--workload", default="modes2d",
-                    choices=["modes2d", "planewave_te", "planewave_3d", "batch", "adjoint", "chebyshev", "chebyshev_3d"],
+                    choices=["modes2d", "planewave_te", "planewave_3d", "batch", "adjoint", "chebyshev", "chebyshev_3d",
+                             "pic"],
                     help="modes2d (default): the 4096^2 line above; the others time the 128^2 TE "
                          "tolerance solve, the 512^3 3D solve, the 64-grid batch, the adjoint and the "
                          "Chebyshev solve against Alg 1 in 2D (chebyshev) and 3D (chebyshev_3d)")
@@ -581,7 +582,65 @@ def bench_chebyshev(steps, warm):
                  a["chebyshev"]["Gcell_steps_per_s"], "Gcell-steps/s", {"steps": steps, "results": out})
 
 
-OTHER_WORKLOADS = {"planewave_te": bench_planewave_te, "planewave_3d": bench_planewave_3d,
+def bench_pic(steps, warm):
+    """Coupled particle-field steps on a drifting pair plasma shaped like the
+    paper's NCI test problem (Table 1): 256 x 128 cells, 256 particles per
+    cell and species (16.8 M in all), drift Lorentz factor 1000, temperature
+    0.01 m c^2, dt = 0.5 dt_CFL, linear shapes; field step m = 20 with a
+    3-pass filter of the deposited current; FP32."""
+    import math
+    import torch
+    from paper_1907_13088_amd import inputs as I
+    from paper_1907_13088_amd import mx
+    steps = steps or 200
+    warm = 5 if warm is None else warm
+    nx, ny = 256, 128
+    t0 = time.time()
+    sps = I.drifting_pair_plasma(n=(nx, ny), ppc=256, dtype="f32")
+    log(f"plasma generated in {time.time() - t0:.1f}s")
+    dt = 0.5 / math.sqrt(2.0)
+    g = mx.Grid(mx.make_config(2, (nx, ny), dt, (1.0, 1.0), "f32", mx.MX_ALL, 20, 0.0, 3))
+    E = [torch.zeros((ny, nx), dtype=torch.float32, device="cuda") for _ in range(3)]
+    B = [torch.zeros((ny, nx), dtype=torch.float32, device="cuda") for _ in range(3)]
+    J = [torch.zeros((ny, nx), dtype=torch.float32, device="cuda") for _ in range(3)]
+    g.bind(E, B)
+    g.set_current(J)
+    parts = [([torch.tensor(sp.x, dtype=torch.float32, device="cuda"),
+               torch.tensor(sp.y, dtype=torch.float32, device="cuda")],
+              [torch.tensor(a, dtype=torch.float32, device="cuda") for a in sp.u]) for sp in sps]
+    npart = sum(int(p[0][0].numel()) for p in parts)
+
+    def one_step():
+        for k, (sp, (pos, u)) in enumerate(zip(sps, parts)):
+            g.pic_push(sp.q, sp.m, sp.w, pos, u, J, accumulate=k > 0)
+        g.step(1, env=[1.0])
+
+    for _ in range(warm):
+        one_step()
+    torch.cuda.synchronize()
+    g.profile_enable(True)
+    s0, s1 = _events()
+    s0.record()
+    for _ in range(steps):
+        one_step()
+    s1.record()
+    torch.cuda.synchronize()
+    ms = s0.elapsed_time(s1)
+    prof = g.profile_read()
+    g.close()
+    pp = prof["particles"]
+    field_ms = sum(v["ms"] for k, v in prof.items() if k != "particles")
+    return _line("coupled particle-field step, drifting pair plasma 256x128, 16.8M particles, FP32",
+                 npart * steps / (ms / 1e3) / 1e9, "Gparticle-steps/s",
+                 {"steps": steps, "dtype": "f32", "particles": npart, "ms_per_step": round(ms / steps, 4),
+                  "push_deposit_us_per_species": round(1e3 * pp["ms"] / max(pp["launches"], 1), 1),
+                  "push_share_of_kernel_time": round(pp["ms"] / max(pp["ms"] + field_ms, 1e-9), 4),
+                  "field_step_us": round(1e3 * field_ms / steps, 1),
+                  "push_phase_space_GBps": round(pp["bytes"] / (pp["ms"] / 1e3) / 1e9, 1) if pp["ms"] else None,
+                  "note": "kernel times from HIP events on every launch (profiling on)"})
+
+
+OTHER_WORKLOADS = {"planewave_te": bench_planewave_te, "planewave_3d": bench_planewave_3d, "pic": bench_pic,
                    "batch": bench_batch, "adjoint": bench_adjoint, "chebyshev": bench_chebyshev,
                    "chebyshev_3d": bench_chebyshev_3d}
 

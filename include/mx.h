@@ -237,7 +237,8 @@ int mx_step_static(const mx_config *cfg, void *stream, void *const E[3], void *c
 #define MX_PROF_OTHER      2  /* separate E increments, FP64 reductions, copies */
 #define MX_PROF_ADJOINT    3  /* transposed curls and the filter of the adjoint */
 #define MX_PROF_SWEEP_LAST 4  /* final sweep passes with E += result fused */
-#define MX_PROF_NCAT       5
+#define MX_PROF_PARTICLES  5  /* particle push and deposition (bytes: the phase space read and written) */
+#define MX_PROF_NCAT       6
 typedef struct mx_profile {
     int64_t launches[MX_PROF_NCAT];
     double ms[MX_PROF_NCAT];     /* summed kernel time per category */
@@ -265,6 +266,40 @@ int mx_profile_read(mx_grid *g, mx_profile *out);
  * ------------------------------------------------------------------------ */
 int mx_adjoint(mx_grid *g, int nsteps, const double *env, const int *sweeps,
                void *const Ebar[3], void *const Bbar[3], void *const dJ0[3]);
+
+/* ------------------------------------------------------------------------
+ * Particle coupling (2D grids, three velocity components).  The paper runs
+ * the field solver inside a particle-in-cell code and keeps that code's
+ * force interpolation, current deposition and particle push (Sec. 2); with
+ * a charge-conserving deposition Gauss's law for E is kept (Sec. 2,
+ * Appendix A).  A coupled step is: mx_pic_push for every species (J^{n+1/2}
+ * from the moves), then mx_step(g, 1, env = {1.0}, ...) with J0 bound to J
+ * (mx_set_current), which filters it and advances the fields.
+ *
+ * mx_pic_push: one push of np particles of charge q, mass m (> 0) and
+ * weight w (macro-particle: charge q w) in the bound E^n and
+ * B^n = B^{n-1/2} - (dt/2) curl E^n, by the relativistic Boris scheme
+ * (Boris 1970; c = 1), fields interpolated with first-order B-spline shapes
+ * at each component's staggered position (the lowest order of Table 1);
+ * then the move and Esirkepov's charge-conserving deposition (Esirkepov
+ * 2001) of J^{n+1/2}, so that rho^{n+1} - rho^n + dt D.J^{n+1/2} = 0 at the
+ * nodes.  pos[2] = x, y (device, np values in the grid dtype; physical
+ * coordinates, node (i, j) at (i dx, j dy), in [0, L); in: n, out: n + 1,
+ * wrapped), u[3] = gamma v (in: n - 1/2, out: n + 1/2).  J[3] (device,
+ * placed like E) is overwritten (accumulate = 0) or added to (1, further
+ * species).  J is a current density per cell area.  A particle moves less
+ * than a cell per step: |v| < 1 and dt obeys the CFL bound.  The
+ * deposition adds with floating-point atomics: J is reproducible up to the
+ * order of those additions (rounding).  Needs blocks = MX_ALL; the bound
+ * fields are read, not changed.
+ *
+ * mx_pic_charge: rho at the nodes (i, j) (device, grid dtype) of the same
+ * particles, the density whose change the deposition's current carries;
+ * overwritten (accumulate = 0) or added to.
+ * ------------------------------------------------------------------------ */
+int mx_pic_push(mx_grid *g, int64_t np, double q, double m, double w, void *const pos[2], void *const u[3],
+                void *const J[3], int accumulate);
+int mx_pic_charge(mx_grid *g, int64_t np, double q, double w, void *const pos[2], void *rho, int accumulate);
 
 /* ------------------------------------------------------------------------
  * Localised 2D source shapes.  Source s has three W x W windows

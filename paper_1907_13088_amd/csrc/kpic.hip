@@ -1,0 +1,196 @@
+// Particle coupling of the 2D field step (arXiv 1907.13088: the solver runs
+// inside a particle-in-cell code whose force interpolation, deposition and
+// push it leaves unchanged, Sec. 2; Gauss's law for E holds when the
+// deposition conserves charge, Sec. 2 and Appendix A):
+//   push ........ relativistic Boris scheme (Boris 1970) in E^n and
+//                 B^n = B^{n-1/2} - (dt/2) curl E^n, c = 1
+//   shapes ...... first-order B-spline at each component's staggered
+//                 position (the lowest order of the paper's Table 1)
+//   deposition .. Esirkepov's charge-conserving decomposition (Esirkepov
+//                 2001), 2D with an out-of-plane current, added with
+//                 hardware floating-point atomics
+// One thread per particle.  Positions are at time level n, momenta
+// u = gamma v at n - 1/2; after the call positions are at n + 1 (wrapped
+// into [0, L)), momenta at n + 1/2, and J holds J^{n+1/2}.
+//
+// A particle moves less than one cell per axis per step: |v| < c and the
+// time step obeys the CFL bound dt <= (1/dx^2 + 1/dy^2)^(-1/2) < min(dx, dy),
+// so the 4 x 4 node window starting one node before the start cell covers
+// both shapes.
+#include "mx_internal.h"
+
+namespace mx {
+namespace {
+
+constexpr int PT = 256;
+
+template <typename T>
+__device__ __forceinline__ T shape1(T d)
+{
+    d = fabs(d);
+    return d < T(1) ? T(1) - d : T(0);
+}
+
+__device__ __forceinline__ int wrapn(int i, int n)
+{
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+template <typename T>
+__global__ __launch_bounds__(PT) void k_pic_push(PicArgs<T> a)
+{
+    const int64_t p = (int64_t)blockIdx.x * PT + threadIdx.x;
+    if (p >= a.np) return;
+    const int nx = a.nx, ny = a.ny;
+    const T dx = a.dx, dy = a.dy, dt = a.dt, th = a.th;
+    auto at = [&](const T *F, int i, int j) { return F[(size_t)wrapn(j, ny) * nx + wrapn(i, nx)]; };
+    const T x0 = a.x[p], y0 = a.y[p];
+    // value of a field at the particle: linear shapes around the component's
+    // staggered position (i + ox, j + oy); val(i, j) is the node value
+    auto gather = [&](auto &&val, T ox, T oy) {
+        const T xi = x0 / dx - ox, eta = y0 / dy - oy;
+        const int i0 = (int)floor(xi), j0 = (int)floor(eta);
+        T v = T(0);
+        for (int b = 0; b < 2; b++)
+            for (int c = 0; c < 2; c++) {
+                const T wgt = shape1(xi - T(i0 + c)) * shape1(eta - T(j0 + b));
+                v += wgt * val(i0 + c, j0 + b);
+            }
+        return v;
+    };
+    const T *Ex = a.E[0], *Ey = a.E[1], *Ez = a.E[2];
+    const T ex = gather([&](int i, int j) { return at(Ex, i, j); }, T(0.5), T(0));
+    const T ey = gather([&](int i, int j) { return at(Ey, i, j); }, T(0), T(0.5));
+    const T ez = gather([&](int i, int j) { return at(Ez, i, j); }, T(0), T(0));
+    // B^n at the B positions: half a Faraday step (eqs faraday_*, 2D)
+    const T bx = gather([&](int i, int j) {
+        const T dyEz = (at(Ez, i, j + 1) - at(Ez, i, j)) / dy;
+        return at(a.B[0], i, j) - th * (dyEz - T(0));
+    }, T(0), T(0.5));
+    const T by = gather([&](int i, int j) {
+        const T dxEz = (at(Ez, i + 1, j) - at(Ez, i, j)) / dx;
+        return at(a.B[1], i, j) - th * (T(0) - dxEz);
+    }, T(0.5), T(0));
+    const T bz = gather([&](int i, int j) {
+        const T dxEy = (at(Ey, i + 1, j) - at(Ey, i, j)) / dx;
+        const T dyEx = (at(Ex, i, j + 1) - at(Ex, i, j)) / dy;
+        return at(a.B[2], i, j) - th * (dxEy - dyEx);
+    }, T(0.5), T(0.5));
+    // Boris: half electric kick, rotation about B, half electric kick
+    const T h = a.h;
+    const T umx = a.ux[p] + h * ex, umy = a.uy[p] + h * ey, umz = a.uz[p] + h * ez;
+    const T gm = sqrt(T(1) + umx * umx + umy * umy + umz * umz);
+    const T tx = h * bx / gm, ty = h * by / gm, tz = h * bz / gm;
+    const T upx = umx + (umy * tz - umz * ty);
+    const T upy = umy + (umz * tx - umx * tz);
+    const T upz = umz + (umx * ty - umy * tx);
+    const T f = T(2) / (T(1) + tx * tx + ty * ty + tz * tz);
+    const T sx = f * tx, sy = f * ty, sz = f * tz;
+    const T uplx = umx + (upy * sz - upz * sy);
+    const T uply = umy + (upz * sx - upx * sz);
+    const T uplz = umz + (upx * sy - upy * sx);
+    const T nux = uplx + h * ex, nuy = uply + h * ey, nuz = uplz + h * ez;
+    const T g = sqrt(T(1) + nux * nux + nuy * nuy + nuz * nuz);
+    const T x1 = x0 + dt * nux / g, y1 = y0 + dt * nuy / g;
+    // Esirkepov: shapes of the start and end positions on the window of
+    // nodes i0 .. i0 + 3, j0 .. j0 + 3
+    const T xi0 = x0 / dx, eta0 = y0 / dy, xi1 = x1 / dx, eta1 = y1 / dy;
+    const int i0 = (int)floor(xi0) - 1, j0 = (int)floor(eta0) - 1;
+    T sx0[4], sx1[4], sy0[4], sy1[4];
+    for (int k = 0; k < 4; k++) {
+        sx0[k] = shape1(xi0 - T(i0 + k));
+        sx1[k] = shape1(xi1 - T(i0 + k));
+        sy0[k] = shape1(eta0 - T(j0 + k));
+        sy1[k] = shape1(eta1 - T(j0 + k));
+    }
+    const T vz = nuz / g;
+    for (int l = 0; l < 4; l++) {
+        T run = T(0);   // sum of W_x over the window's nodes up to k
+        for (int k = 0; k < 3; k++) {
+            run += T(0.5) * (sx1[k] - sx0[k]) * (sy0[l] + sy1[l]);
+            const T v = a.cx * run;
+            if (v != T(0)) unsafeAtomicAdd(&a.J[0][(size_t)wrapn(j0 + l, ny) * nx + wrapn(i0 + k, nx)], v);
+        }
+    }
+    for (int k = 0; k < 4; k++) {
+        T run = T(0);   // sum of W_y over the window's nodes up to l
+        for (int l = 0; l < 3; l++) {
+            run += T(0.5) * (sy1[l] - sy0[l]) * (sx0[k] + sx1[k]);
+            const T v = a.cy * run;
+            if (v != T(0)) unsafeAtomicAdd(&a.J[1][(size_t)wrapn(j0 + l, ny) * nx + wrapn(i0 + k, nx)], v);
+        }
+    }
+    for (int l = 0; l < 4; l++)
+        for (int k = 0; k < 4; k++) {
+            const T wz = (T(2) * sx0[k] * sy0[l] + sx1[k] * sy0[l] + sx0[k] * sy1[l] + T(2) * sx1[k] * sy1[l]) / T(6);
+            const T v = a.cz * vz * wz;
+            if (v != T(0)) unsafeAtomicAdd(&a.J[2][(size_t)wrapn(j0 + l, ny) * nx + wrapn(i0 + k, nx)], v);
+        }
+    a.x[p] = x1 >= a.Lx ? x1 - a.Lx : (x1 < T(0) ? x1 + a.Lx : x1);
+    a.y[p] = y1 >= a.Ly ? y1 - a.Ly : (y1 < T(0) ? y1 + a.Ly : y1);
+    a.ux[p] = nux;
+    a.uy[p] = nuy;
+    a.uz[p] = nuz;
+}
+
+// rho at the nodes += q w / (dx dy) S(x/dx - i) S(y/dy - j)
+template <typename T>
+__global__ __launch_bounds__(PT) void k_pic_charge(int64_t np, int nx, int ny, T dx, T dy, T cq, const T *x,
+                                                   const T *y, T *rho)
+{
+    const int64_t p = (int64_t)blockIdx.x * PT + threadIdx.x;
+    if (p >= np) return;
+    const T xi = x[p] / dx, eta = y[p] / dy;
+    const int i0 = (int)floor(xi), j0 = (int)floor(eta);
+    for (int b = 0; b < 2; b++)
+        for (int c = 0; c < 2; c++) {
+            const T v = cq * shape1(xi - T(i0 + c)) * shape1(eta - T(j0 + b));
+            if (v != T(0)) unsafeAtomicAdd(&rho[(size_t)wrapn(j0 + b, ny) * nx + wrapn(i0 + c, nx)], v);
+        }
+}
+
+template <typename T>
+__global__ __launch_bounds__(PT) void k_fill0(int64_t n, T *a, T *b, T *c)
+{
+    const int64_t i = (int64_t)blockIdx.x * PT + threadIdx.x;
+    if (i >= n) return;
+    a[i] = T(0);
+    if (b) b[i] = T(0);
+    if (c) c[i] = T(0);
+}
+
+unsigned blocks_for(int64_t n) { return (unsigned)((n + PT - 1) / PT); }
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_pic_push(const PicArgs<T> &a, bool zero_j, hipStream_t s)
+{
+    const int64_t ncell = (int64_t)a.nx * a.ny;
+    if (zero_j && ncell > 0)
+        hipLaunchKernelGGL((k_fill0<T>), dim3(blocks_for(ncell)), dim3(PT), 0, s, ncell, a.J[0], a.J[1], a.J[2]);
+    if (a.np > 0) hipLaunchKernelGGL((k_pic_push<T>), dim3(blocks_for(a.np)), dim3(PT), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pic_charge(int64_t np, int nx, int ny, T dx, T dy, T cq, const T *x, const T *y, T *rho,
+                             bool zero_rho, hipStream_t s)
+{
+    const int64_t ncell = (int64_t)nx * ny;
+    if (zero_rho && ncell > 0)
+        hipLaunchKernelGGL((k_fill0<T>), dim3(blocks_for(ncell)), dim3(PT), 0, s, ncell, rho, (T *)nullptr,
+                           (T *)nullptr);
+    if (np > 0) hipLaunchKernelGGL((k_pic_charge<T>), dim3(blocks_for(np)), dim3(PT), 0, s, np, nx, ny, dx, dy, cq, x, y, rho);
+    return hipGetLastError();
+}
+
+template hipError_t launch_pic_push<float>(const PicArgs<float> &, bool, hipStream_t);
+template hipError_t launch_pic_push<double>(const PicArgs<double> &, bool, hipStream_t);
+template hipError_t launch_pic_charge<float>(int64_t, int, int, float, float, float, const float *, const float *,
+                                             float *, bool, hipStream_t);
+template hipError_t launch_pic_charge<double>(int64_t, int, int, double, double, double, const double *,
+                                              const double *, double *, bool, hipStream_t);
+
+}  // namespace mx

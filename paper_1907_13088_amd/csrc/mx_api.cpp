@@ -1057,6 +1057,97 @@ int mx_adjoint(mx_grid *g, int nsteps, const double *env, const int *sweeps, voi
                                   : adjoint_impl<float>(g, nsteps, env, sweeps, Ebar, Bbar, dJ0);
 }
 
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+int pic_push_impl(mx_grid *g, int64_t np, double q, double m, double w, void *const pos[2], void *const u[3],
+                  void *const J[3], bool zero_j)
+{
+    const mx_config &c = g->cfg;
+    PicArgs<T> a{};
+    for (int q3 = 0; q3 < 3; q3++) {
+        a.E[q3] = (const T *)g->E[q3];
+        a.B[q3] = (const T *)g->B[q3];
+        a.J[q3] = (T *)J[q3];
+    }
+    a.x = (T *)(np ? pos[0] : nullptr);
+    a.y = (T *)(np ? pos[1] : nullptr);
+    a.ux = (T *)(np ? u[0] : nullptr);
+    a.uy = (T *)(np ? u[1] : nullptr);
+    a.uz = (T *)(np ? u[2] : nullptr);
+    a.np = np;
+    a.nx = (int)c.n[0];
+    a.ny = (int)c.n[1];
+    a.dx = (T)c.d[0];
+    a.dy = (T)c.d[1];
+    a.dt = (T)c.dt;
+    a.th = (T)(0.5 * c.dt);
+    a.h = (T)(q * c.dt / (2.0 * m));
+    a.cx = (T)(-q * w / (c.d[1] * c.dt));
+    a.cy = (T)(-q * w / (c.d[0] * c.dt));
+    a.cz = (T)(q * w / (c.d[0] * c.d[1]));
+    a.Lx = (T)(c.n[0] * c.d[0]);
+    a.Ly = (T)(c.n[1] * c.d[1]);
+    ProfScope ps(g, MX_PROF_PARTICLES, (double)np * sizeof(T) * 10);
+    HIPCHK(launch_pic_push<T>(a, zero_j, g->stream));
+    return MX_OK;
+}
+
+int pic_check(mx_grid *g, int64_t np)
+{
+    if (!g) return fail(MX_EINVAL, "grid is NULL");
+    if (g->cfg.ndim != 2) return fail(MX_EINVAL, "the particle coupling is 2D");
+    if (np < 0 || np > (int64_t)0x7fffffff * 256) return fail(MX_EINVAL, "np out of range");
+    return MX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mx_pic_push(mx_grid *g, int64_t np, double q, double m, double w, void *const pos[2], void *const u[3],
+                void *const J[3], int accumulate)
+{
+    int rc = pic_check(g, np);
+    if (rc) return rc;
+    if (!g->bound) return fail(MX_ESTATE, "mx_pic_push before mx_bind_fields");
+    if (g->cfg.blocks != MX_ALL) return fail(MX_EINVAL, "the particle push needs both 2D blocks (MX_ALL)");
+    if (!(m > 0.0) || !std::isfinite(m) || !std::isfinite(q) || !std::isfinite(w))
+        return fail(MX_EINVAL, "q, w must be finite and m positive");
+    if (!J || !J[0] || !J[1] || !J[2]) return fail(MX_EINVAL, "J is NULL");
+    if (np > 0) {
+        if (!pos || !pos[0] || !pos[1] || !u || !u[0] || !u[1] || !u[2])
+            return fail(MX_EINVAL, "particle arrays are NULL");
+    }
+    HIPCHK(hipSetDevice(g->device));
+    return g->cfg.dtype == MX_F64 ? pic_push_impl<double>(g, np, q, m, w, pos, u, J, accumulate == 0)
+                                  : pic_push_impl<float>(g, np, q, m, w, pos, u, J, accumulate == 0);
+}
+
+int mx_pic_charge(mx_grid *g, int64_t np, double q, double w, void *const pos[2], void *rho, int accumulate)
+{
+    int rc = pic_check(g, np);
+    if (rc) return rc;
+    if (!std::isfinite(q) || !std::isfinite(w)) return fail(MX_EINVAL, "q, w must be finite");
+    if (!rho) return fail(MX_EINVAL, "rho is NULL");
+    if (np > 0 && (!pos || !pos[0] || !pos[1])) return fail(MX_EINVAL, "positions are NULL");
+    HIPCHK(hipSetDevice(g->device));
+    const mx_config &c = g->cfg;
+    const double cq = q * w / (c.d[0] * c.d[1]);
+    const int nx = (int)c.n[0], ny = (int)c.n[1];
+    if (c.dtype == MX_F64)
+        HIPCHK(launch_pic_charge<double>(np, nx, ny, c.d[0], c.d[1], cq, np ? (const double *)pos[0] : nullptr,
+                                         np ? (const double *)pos[1] : nullptr, (double *)rho, accumulate == 0,
+                                         g->stream));
+    else
+        HIPCHK(launch_pic_charge<float>(np, nx, ny, (float)c.d[0], (float)c.d[1], (float)cq,
+                                        np ? (const float *)pos[0] : nullptr, np ? (const float *)pos[1] : nullptr,
+                                        (float *)rho, accumulate == 0, g->stream));
+    return MX_OK;
+}
+
 int mx_sources_assemble(mx_grid *g, int nsrc, int W, const int64_t *origins, const void *shapes,
                         const void *amps, void *const J0[3])
 {

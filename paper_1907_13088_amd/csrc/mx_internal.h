@@ -218,6 +218,28 @@ int step_on_scratch(const mx_config *cfg, void *stream, int device, void *ws, si
                     void *const B[3], void *const J0[3], int nsteps, const double *env, const int *replay,
                     mx_step_stats *stats);
 
+// Particle push and charge-conserving deposition, 2D (kpic.hip)
+template <typename T>
+struct PicArgs {
+    const T *E[3];        // E^n
+    const T *B[3];        // B^{n-1/2}
+    T *x, *y;             // positions (in: n, out: n + 1, wrapped into [0, L))
+    T *ux, *uy, *uz;      // u = gamma v (in: n - 1/2, out: n + 1/2)
+    T *J[3];              // J^{n+1/2} is added here
+    int64_t np;
+    int nx, ny;
+    T dx, dy, dt;
+    T th;                 // dt / 2: B^n = B^{n-1/2} - th curl E^n
+    T h;                  // q dt / (2 m)
+    T cx, cy, cz;         // -q w / (dy dt), -q w / (dx dt), q w / (dx dy)
+    T Lx, Ly;             // nx dx, ny dy
+};
+template <typename T>
+hipError_t launch_pic_push(const PicArgs<T> &a, bool zero_j, hipStream_t s);
+template <typename T>
+hipError_t launch_pic_charge(int64_t np, int nx, int ny, T dx, T dy, T cq, const T *x, const T *y, T *rho,
+                             bool zero_rho, hipStream_t s);
+
 // Fused 3D front (k3f.hip): Faraday into a.B from Bin, p <= front3d_max_passes()
 // filter passes of the current, dE' (and its FP64 partial norms when
 // a.partial is set); *nwg receives the workgroup count

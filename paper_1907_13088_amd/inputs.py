@@ -422,3 +422,54 @@ def assemble_sources(n: int, origins, shapes, amps) -> List[np.ndarray]:
         for c in range(3):
             np.add.at(J[c], np.ix_(ys, xs), amps[s] * shapes[s, c])
     return J
+
+
+# --------------------------------------------------------------------------
+# Particles for the coupled step: a drifting pair plasma
+# --------------------------------------------------------------------------
+
+@dataclass
+class Species:
+    q: float
+    m: float
+    w: float                     # macro-particle weight (charge q w)
+    x: np.ndarray
+    y: np.ndarray
+    u: List[np.ndarray]          # gamma v, three components
+
+
+def drifting_pair_plasma(n: Tuple[int, int] = (256, 128), ppc: int = 256, gamma: float = 1000.0,
+                         temperature: float = 0.01, skin_depth: float = 16.0, seed: int = 1006,
+                         dtype: str = "f32") -> List[Species]:
+    """Electrons and positrons (q = -1, +1, m = 1, c = 1) drifting along +x,
+    the shape of the paper's NCI test problem (Table 1: 256 x 128 cells, 256
+    particles per cell and species, drift Lorentz factor 1000, temperature
+    0.01 m c^2, domain 16 x 8 skin depths, so 16 cells per skin depth).
+    Positions are uniform over the periodic domain (unit cells).  Momenta:
+    a Maxwellian of temperature T in the rest frame (u_i ~ N(0, T/m) per
+    axis, gamma from |u|), boosted along x with the drift Lorentz factor
+    (u_x' = gamma_d (u_x + beta_d gamma), u_y, u_z unchanged); a synthetic
+    stand-in for the relativistic shifted-Maxwellian loader the paper uses.
+    The weight makes the skin depth c / omega_p with
+    omega_p^2 = 4 pi q^2 n / (gamma m) equal `skin_depth` cells:
+    n = gamma / (4 pi skin_depth^2) per species and cell."""
+    rng = np.random.default_rng(seed)
+    nx, ny = n
+    npart = nx * ny * ppc
+    np_dt = np.float32 if dtype == "f32" else np.float64
+    dens = gamma / (FOUR_PI * skin_depth * skin_depth)
+    beta = math.sqrt(1.0 - 1.0 / (gamma * gamma))
+    out = []
+    for q in (-1.0, 1.0):
+        x = rng.uniform(0.0, nx, npart)
+        y = rng.uniform(0.0, ny, npart)
+        th = math.sqrt(temperature)
+        u0 = [rng.normal(0.0, th, npart) for _ in range(3)]
+        g0 = np.sqrt(1.0 + u0[0] ** 2 + u0[1] ** 2 + u0[2] ** 2)
+        ux = gamma * (u0[0] + beta * g0)
+        # positions strictly inside [0, L) after rounding to the run dtype
+        x = np.minimum(round_to(np_dt, x), np.nextafter(np.asarray(nx, np_dt), np_dt(0)).astype(np.float64))
+        y = np.minimum(round_to(np_dt, y), np.nextafter(np.asarray(ny, np_dt), np_dt(0)).astype(np.float64))
+        out.append(Species(q=q, m=1.0, w=float(round_to(np_dt, dens / ppc)), x=x, y=y,
+                           u=[round_to(np_dt, ux), round_to(np_dt, u0[1]), round_to(np_dt, u0[2])]))
+    return out

@@ -29,7 +29,7 @@ EXPORTS = ["mx_profile_enable", "mx_profile_read", "mx_last_error", "mx_config_d
            "mx_get_sweeps_per_pass", "mx_get_block_sweeps_per_pass", "mx_destroy", "mx_adjoint", "mx_sources_assemble",
            "mx_sources_project", "mx_batch_workspace_size", "mx_batch_init", "mx_batch_bind",
            "mx_batch_step", "mx_batch_get_plan", "mx_batch_get_schedule", "mx_batch_destroy",
-           "mx_step_static"]
+           "mx_step_static", "mx_pic_push", "mx_pic_charge"]
 STATIC_SCRATCH_BYTES = 64 << 20   # MX_STATIC_SCRATCH_BYTES
 
 
@@ -48,10 +48,10 @@ class CConfig(C.Structure):
 
 
 class CProfile(C.Structure):
-    _fields_ = [("launches", C.c_int64 * 5), ("ms", C.c_double * 5), ("bytes", C.c_double * 5)]
+    _fields_ = [("launches", C.c_int64 * 6), ("ms", C.c_double * 6), ("bytes", C.c_double * 6)]
 
 
-PROF_CATEGORIES = ("front", "sweep", "other", "adjoint", "sweep_last")
+PROF_CATEGORIES = ("front", "sweep", "other", "adjoint", "sweep_last", "particles")
 
 
 class CStats(C.Structure):
@@ -96,6 +96,8 @@ def lib():
         L.mx_sources_project.argtypes = [vp, C.c_int, C.c_int, vp, vp, P(vp), vp]
         L.mx_step_static.argtypes = [P(CConfig), vp, P(vp), P(vp), P(vp), C.c_int, P(C.c_double), P(C.c_int),
                                      P(CStats)]
+        L.mx_pic_push.argtypes = [vp, C.c_int64, C.c_double, C.c_double, C.c_double, P(vp), P(vp), P(vp), C.c_int]
+        L.mx_pic_charge.argtypes = [vp, C.c_int64, C.c_double, C.c_double, P(vp), vp, C.c_int]
         if hasattr(L, "mx_batch_init"):
             L.mx_batch_workspace_size.argtypes = [P(CConfig), C.c_int, P(C.c_size_t)]
             L.mx_batch_init.argtypes = [P(CConfig), C.c_int, vp, vp, C.c_size_t, P(vp)]
@@ -285,6 +287,26 @@ class Grid:
         nsrc, W = int(shapes.shape[0]), int(shapes.shape[-1])
         _check(lib().mx_sources_project(self.h, nsrc, W, C.c_void_p(origins.data_ptr()),
                                         C.c_void_p(shapes.data_ptr()), _ptrs(G), C.c_void_p(grad.data_ptr())))
+
+    def pic_push(self, q: float, m: float, w: float, pos: Sequence, u: Sequence, J: Sequence,
+                 accumulate: bool = False):
+        """One Boris push of a species (pos = (x, y), u = gamma v, device
+        vectors in the grid dtype, updated in place) in the bound fields; its
+        current J^{n+1/2} overwrites J (or is added with accumulate=True)."""
+        np_ = int(pos[0].numel())
+        for t in list(pos) + list(u):
+            if t.dtype != self.torch_dtype or not t.is_contiguous() or t.numel() != np_:
+                raise ValueError("particle arrays must be contiguous vectors of one length in the grid dtype")
+        for t in J:
+            self._check_field(t)
+        _check(lib().mx_pic_push(self.h, np_, float(q), float(m), float(w), _ptrs(pos), _ptrs(u), _ptrs(J),
+                                 int(bool(accumulate))))
+
+    def pic_charge(self, q: float, w: float, pos: Sequence, rho, accumulate: bool = False):
+        """Charge density of a species at the nodes (overwrites rho, or adds)."""
+        self._check_field(rho)
+        _check(lib().mx_pic_charge(self.h, int(pos[0].numel()), float(q), float(w), _ptrs(pos),
+                                   C.c_void_p(rho.data_ptr()), int(bool(accumulate))))
 
     def profile_enable(self, on: bool = True):
         """True: reset the per-kernel timers and record; False: pause."""
