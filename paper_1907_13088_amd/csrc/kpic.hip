@@ -8,7 +8,9 @@
 //                 position (the lowest order of the paper's Table 1)
 //   deposition .. Esirkepov's charge-conserving decomposition (Esirkepov
 //                 2001), 2D with an out-of-plane current, added with
-//                 hardware floating-point atomics
+//                 floating-point atomics: in LDS when the windows of a
+//                 workgroup's particles fit one tile (particles kept in cell
+//                 order), then once per node into J; else directly into J
 // One thread per particle.  Positions are at time level n, momenta
 // u = gamma v at n - 1/2; after the call positions are at n + 1 (wrapped
 // into [0, L)), momenta at n + 1/2, and J holds J^{n+1/2}.
@@ -37,15 +39,36 @@ __device__ __forceinline__ int wrapn(int i, int n)
     return i < 0 ? i + n : i;
 }
 
+// LDS accumulation tile of the deposition (nodes)
+constexpr int TWX = 32, TWY = 32;
+
+// min and max of v over the workgroup (valid in every thread)
+__device__ __forceinline__ void block_minmax(int &vmin, int &vmax, int *sh)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        vmin = min(vmin, __shfl_xor(vmin, off, 64));
+        vmax = max(vmax, __shfl_xor(vmax, off, 64));
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) { sh[2 * w] = vmin; sh[2 * w + 1] = vmax; }
+    __syncthreads();
+    vmin = sh[0];
+    vmax = sh[1];
+    for (int q = 1; q < PT / 64; q++) { vmin = min(vmin, sh[2 * q]); vmax = max(vmax, sh[2 * q + 1]); }
+}
+
 template <typename T>
 __global__ __launch_bounds__(PT) void k_pic_push(PicArgs<T> a)
 {
+    __shared__ T tile[3][TWY][TWX];
+    __shared__ int sh[2 * PT / 64];
     const int64_t p = (int64_t)blockIdx.x * PT + threadIdx.x;
-    if (p >= a.np) return;
+    const bool live = p < a.np;
     const int nx = a.nx, ny = a.ny;
     const T dx = a.dx, dy = a.dy, dt = a.dt, th = a.th;
     auto at = [&](const T *F, int i, int j) { return F[(size_t)wrapn(j, ny) * nx + wrapn(i, nx)]; };
-    const T x0 = a.x[p], y0 = a.y[p];
+    const T x0 = live ? a.x[p] : T(0), y0 = live ? a.y[p] : T(0);
     // value of a field at the particle: linear shapes around the component's
     // staggered position (i + ox, j + oy); val(i, j) is the node value
     auto gather = [&](auto &&val, T ox, T oy) {
@@ -79,7 +102,8 @@ __global__ __launch_bounds__(PT) void k_pic_push(PicArgs<T> a)
     }, T(0.5), T(0.5));
     // Boris: half electric kick, rotation about B, half electric kick
     const T h = a.h;
-    const T umx = a.ux[p] + h * ex, umy = a.uy[p] + h * ey, umz = a.uz[p] + h * ez;
+    const T umx = (live ? a.ux[p] : T(0)) + h * ex, umy = (live ? a.uy[p] : T(0)) + h * ey,
+            umz = (live ? a.uz[p] : T(0)) + h * ez;
     const T gm = sqrt(T(1) + umx * umx + umy * umy + umz * umz);
     const T tx = h * bx / gm, ty = h * by / gm, tz = h * bz / gm;
     const T upx = umx + (umy * tz - umz * ty);
@@ -105,33 +129,62 @@ __global__ __launch_bounds__(PT) void k_pic_push(PicArgs<T> a)
         sy1[k] = shape1(eta1 - T(j0 + k));
     }
     const T vz = nuz / g;
-    for (int l = 0; l < 4; l++) {
-        T run = T(0);   // sum of W_x over the window's nodes up to k
-        for (int k = 0; k < 3; k++) {
-            run += T(0.5) * (sx1[k] - sx0[k]) * (sy0[l] + sy1[l]);
-            const T v = a.cx * run;
-            if (v != T(0)) unsafeAtomicAdd(&a.J[0][(size_t)wrapn(j0 + l, ny) * nx + wrapn(i0 + k, nx)], v);
+    // the workgroup's windows: when they fit one LDS tile (particles kept in
+    // cell order), the contributions are summed in LDS and added to J once
+    // per node; otherwise each goes to J directly
+    int imin = live ? i0 : 0x7fffffff, imax = live ? i0 : -0x7fffffff;
+    block_minmax(imin, imax, sh);
+    int jmin = live ? j0 : 0x7fffffff, jmax = live ? j0 : -0x7fffffff;
+    block_minmax(jmin, jmax, sh);
+    const int bw = imax + 4 - imin, bh = jmax + 4 - jmin;
+    const bool in_lds = imax >= imin && bw <= TWX && bh <= TWY;
+    if (in_lds) {
+        for (int e = threadIdx.x; e < 3 * bw * bh; e += PT) {
+            const int c = e / (bw * bh), r = e % (bw * bh);
+            tile[c][r / bw][r % bw] = T(0);
         }
+        __syncthreads();
     }
-    for (int k = 0; k < 4; k++) {
-        T run = T(0);   // sum of W_y over the window's nodes up to l
-        for (int l = 0; l < 3; l++) {
-            run += T(0.5) * (sy1[l] - sy0[l]) * (sx0[k] + sx1[k]);
-            const T v = a.cy * run;
-            if (v != T(0)) unsafeAtomicAdd(&a.J[1][(size_t)wrapn(j0 + l, ny) * nx + wrapn(i0 + k, nx)], v);
+    auto add = [&](int comp, int k, int l, T v) {
+        if (v == T(0)) return;
+        if (in_lds) atomicAdd(&tile[comp][j0 + l - jmin][i0 + k - imin], v);
+        else unsafeAtomicAdd(&a.J[comp][(size_t)wrapn(j0 + l, ny) * nx + wrapn(i0 + k, nx)], v);
+    };
+    if (live) {
+        for (int l = 0; l < 4; l++) {
+            T run = T(0);   // sum of W_x over the window's nodes up to k
+            for (int k = 0; k < 3; k++) {
+                run += T(0.5) * (sx1[k] - sx0[k]) * (sy0[l] + sy1[l]);
+                add(0, k, l, a.cx * run);
+            }
         }
-    }
-    for (int l = 0; l < 4; l++)
         for (int k = 0; k < 4; k++) {
-            const T wz = (T(2) * sx0[k] * sy0[l] + sx1[k] * sy0[l] + sx0[k] * sy1[l] + T(2) * sx1[k] * sy1[l]) / T(6);
-            const T v = a.cz * vz * wz;
-            if (v != T(0)) unsafeAtomicAdd(&a.J[2][(size_t)wrapn(j0 + l, ny) * nx + wrapn(i0 + k, nx)], v);
+            T run = T(0);   // sum of W_y over the window's nodes up to l
+            for (int l = 0; l < 3; l++) {
+                run += T(0.5) * (sy1[l] - sy0[l]) * (sx0[k] + sx1[k]);
+                add(1, k, l, a.cy * run);
+            }
         }
-    a.x[p] = x1 >= a.Lx ? x1 - a.Lx : (x1 < T(0) ? x1 + a.Lx : x1);
-    a.y[p] = y1 >= a.Ly ? y1 - a.Ly : (y1 < T(0) ? y1 + a.Ly : y1);
-    a.ux[p] = nux;
-    a.uy[p] = nuy;
-    a.uz[p] = nuz;
+        for (int l = 0; l < 4; l++)
+            for (int k = 0; k < 4; k++) {
+                const T wz = (T(2) * sx0[k] * sy0[l] + sx1[k] * sy0[l] + sx0[k] * sy1[l] + T(2) * sx1[k] * sy1[l]) / T(6);
+                add(2, k, l, a.cz * vz * wz);
+            }
+        a.x[p] = x1 >= a.Lx ? x1 - a.Lx : (x1 < T(0) ? x1 + a.Lx : x1);
+        a.y[p] = y1 >= a.Ly ? y1 - a.Ly : (y1 < T(0) ? y1 + a.Ly : y1);
+        a.ux[p] = nux;
+        a.uy[p] = nuy;
+        a.uz[p] = nuz;
+    }
+    if (in_lds) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < 3 * bw * bh; e += PT) {
+            const int c = e / (bw * bh), r = e % (bw * bh);
+            const T v = tile[c][r / bw][r % bw];
+            if (v != T(0))
+                unsafeAtomicAdd(&a.J[c][(size_t)wrapn(jmin + r / bw, ny) * nx + wrapn(imin + r % bw, nx)], v);
+        }
+    }
 }
 
 // rho at the nodes += q w / (dx dy) S(x/dx - i) S(y/dy - j)

@@ -470,6 +470,9 @@ def drifting_pair_plasma(n: Tuple[int, int] = (256, 128), ppc: int = 256, gamma:
         # positions strictly inside [0, L) after rounding to the run dtype
         x = np.minimum(round_to(np_dt, x), np.nextafter(np.asarray(nx, np_dt), np_dt(0)).astype(np.float64))
         y = np.minimum(round_to(np_dt, y), np.nextafter(np.asarray(ny, np_dt), np_dt(0)).astype(np.float64))
-        out.append(Species(q=q, m=1.0, w=float(round_to(np_dt, dens / ppc)), x=x, y=y,
-                           u=[round_to(np_dt, ux), round_to(np_dt, u0[1]), round_to(np_dt, u0[2])]))
+        # particles in cell order (row-major), as particle codes keep them
+        order = np.argsort(np.floor(y).astype(np.int64) * nx + np.floor(x).astype(np.int64), kind="stable")
+        u = [ux, u0[1], u0[2]]
+        out.append(Species(q=q, m=1.0, w=float(round_to(np_dt, dens / ppc)), x=x[order], y=y[order],
+                           u=[round_to(np_dt, c[order]) for c in u]))
     return out

@@ -48,12 +48,23 @@ def _rel(got, want):
     return max(float(np.abs(g - w).max()) for g, w in zip(got, want)) / scale
 
 
-@pytest.mark.parametrize("d", [(1.0, 1.0), (0.9, 1.2)])
-def test_push_and_deposit_match_oracle_fp64(d):
+def _cell_order(sp, d, nx):
+    o = np.argsort(np.floor(sp.y / d[1]).astype(np.int64) * nx + np.floor(sp.x / d[0]).astype(np.int64),
+                   kind="stable")
+    return I.Species(q=sp.q, m=sp.m, w=sp.w, x=sp.x[o].copy(), y=sp.y[o].copy(), u=[a[o].copy() for a in sp.u])
+
+
+@pytest.mark.parametrize("d,ordered", [((1.0, 1.0), False), ((0.9, 1.2), False), ((0.9, 1.2), True)])
+def test_push_and_deposit_match_oracle_fp64(d, ordered):
     """One push of two species on a ragged grid: positions, momenta and the
-    accumulated current within 1e-12 of the oracle."""
+    accumulated current within 1e-12 of the oracle, with the particles in
+    random order (every contribution added to J directly) and in cell order
+    (a workgroup's contributions summed in LDS first, except where its
+    particles straddle the periodic seam)."""
     import torch
-    cfg_o, cfg_g, E, B, species = _setup((29, 37), d, "f64", seed=1)
+    cfg_o, cfg_g, E, B, species = _setup((29, 37), d, "f64", seed=1, npart=1500)
+    if ordered:
+        species = [_cell_order(sp, d, 37) for sp in species]
     g = mx.Grid(cfg_g)
     Et, Bt = torch_fields(E, "f64"), torch_fields(B, "f64")
     g.bind(Et, Bt)
