@@ -1,0 +1,332 @@
+#pragma once
+// Single-launch tolerance solve for small 2D grids (Alg. 1 with the stop
+// test of each block, Sec. 2.2.1): grids too small to fill the GPU with
+// row streams spend most of a step in launch gaps (front, one sweep pass,
+// reduction and stop test per pass, E increment).  Here one cooperative
+// launch runs up to SMALL_MAX_STEPS whole steps: per step the front (Faraday,
+// filter of the current, auxiliary increment dE' and its FP64 norm) on each
+// workgroup's tile with a recomputed halo, then passes of the LDS-tile sweep
+// (the same device function as the per-launch kernel, so the iterates are
+// bitwise those of a replay of the same counts), each followed by the FP64
+// reduction of the per-workgroup norms, which every workgroup sums in the
+// same order and so takes the same stop decision, then the E increment.
+// Phases are separated by the bounded grid barrier; workgroup 0 records
+// each step's counts and norms.
+#include "gridbar.h"
+#include "k2tile.h"
+
+namespace mx {
+namespace small2d {
+
+using tile2d::NT;
+
+template <typename T> struct Tile;
+template <> struct Tile<double> { static constexpr int TX = 32, TY = 8; };
+template <> struct Tile<float> { static constexpr int TX = 32, TY = 16; };
+constexpr int PMAX = 4;   // filter passes
+constexpr int KMAX = 8;   // sweeps per pass
+
+template <typename T>
+constexpr size_t front_bytes()
+{
+    constexpr int TX = Tile<T>::TX, TY = Tile<T>::TY;
+    return sizeof(T) * (3 * (TX + 3) * (TY + 3) + 3 * (TX + 2) * (TY + 2) + 3 * (TX + 2 * PMAX) * (TY + 2 * PMAX) +
+                        3 * TX * (TY + 2 * PMAX));
+}
+template <typename T>
+constexpr size_t lds_bytes()
+{
+    constexpr size_t sw = tile2d::sweep_lds_bytes<T, 3, KMAX, Tile<T>::TX, Tile<T>::TY>();
+    return sw > front_bytes<T>() ? sw : front_bytes<T>();
+}
+
+// the filter's x weights: binomial(2P, t) / 4^P
+template <int P>
+__device__ __forceinline__ constexpr float binom(int t)
+{
+    float c = 1.0f;
+    for (int i = 0; i < t; i++) c = c * (float)(2 * P - i) / (float)(i + 1);
+    float d = 1.0f;
+    for (int i = 0; i < P; i++) d *= 4.0f;
+    return c / d;
+}
+
+// alpha f = f + (f- + f+ - 2 f)/6 (sixth = 0: the lumped scheme)
+template <typename T>
+__device__ __forceinline__ T avg6(T fm, T f0, T fp, T sixth)
+{
+    return fma(fma(T(-2), f0, fm + fp), sixth, f0);
+}
+
+// The front of step s on tile (bx, by): B^{n+1/2} on the tile and a
+// one-cell halo, dE' on the tile, its FP64 norm per block in partial[wg].
+// The arithmetic of each output is that of the streaming front kernel.
+template <typename T, int P>
+__device__ __forceinline__ void front(const SmallArgs<T> &a, int s, int bx, int by, int wg, char *lds, double *sred)
+{
+    constexpr int TX = Tile<T>::TX, TY = Tile<T>::TY;
+    constexpr int EX = TX + 3, EY = TY + 3, BX = TX + 2, BY = TY + 2, JX = TX + 2 * P, JY = TY + 2 * P;
+    T(*sE)[EY][EX] = reinterpret_cast<T(*)[EY][EX]>(lds);
+    T(*sB)[BY][BX] = reinterpret_cast<T(*)[BY][BX]>(lds + sizeof(T) * 3 * EY * EX);
+    T(*sJ)[JY][JX] = reinterpret_cast<T(*)[JY][JX]>(lds + sizeof(T) * 3 * (EY * EX + BY * BX));
+    T(*sJx)[JY][TX] = reinterpret_cast<T(*)[JY][TX]>(lds + sizeof(T) * 3 * (EY * EX + BY * BX + JY * JX));
+    const Coef<T> &c = a.c;
+    const int nx = c.nx, ny = c.ny, tid = threadIdx.x;
+    const int X0 = bx * TX, Y0 = by * TY;
+    const bool TE = a.blocks & 1, TM = a.blocks & 2;
+    const bool hasj = a.J0[0] != nullptr;
+    const T sixth = c.lumped ? T(0) : T(1.0 / 6.0);
+    const T es = a.env_src[s];
+    using tile2d::wrapi;
+    const T *Bin[3];
+    T *Bout[3];
+    for (int q = 0; q < 3; q++) {
+        // parity selects without indexing the argument block at run time
+        Bin[q] = (s & 1) ? a.B[1][q] : a.B[0][q];
+        Bout[q] = (s & 1) ? a.B[0][q] : a.B[1][q];
+    }
+    for (int e = tid; e < 3 * EY * EX; e += NT) {
+        const int q = e / (EY * EX), r = e % (EY * EX), iy = r / EX, ix = r % EX;
+        if ((q < 2 && !TE) || (q == 2 && !TM)) continue;
+        sE[q][iy][ix] = a.E[q][(size_t)wrapi(Y0 - 1 + iy, ny) * nx + wrapi(X0 - 1 + ix, nx)];
+    }
+    if (hasj)
+        for (int e = tid; e < 3 * JY * JX; e += NT) {
+            const int q = e / (JY * JX), r = e % (JY * JX), iy = r / JX, ix = r % JX;
+            if ((q < 2 && !TE) || (q == 2 && !TM)) continue;
+            sJ[q][iy][ix] = a.J0[q][(size_t)wrapi(Y0 - P + iy, ny) * nx + wrapi(X0 - P + ix, nx)];
+        }
+    __syncthreads();
+    // B^{n+1/2} = B^{n-1/2} - dt curl E^n on the tile and its halo (the E
+    // tile's cell (ix, iy) is the B region's cell (ix, iy))
+    for (int e = tid; e < BY * BX; e += NT) {
+        const int iy = e / BX, ix = e % BX;
+        const int gx = X0 - 1 + ix, gy = Y0 - 1 + iy;
+        const size_t o = (size_t)wrapi(gy, ny) * nx + wrapi(gx, nx);
+        const bool own = ix >= 1 && ix <= TX && iy >= 1 && iy <= TY && gx < nx && gy < ny;
+        if (TM) {
+            const T ez = sE[2][iy][ix];
+            const T bxv = Bin[0][o] - c.tdy * (sE[2][iy + 1][ix] - ez);
+            const T byv = Bin[1][o] + c.tdx * (sE[2][iy][ix + 1] - ez);
+            sB[0][iy][ix] = bxv;
+            sB[1][iy][ix] = byv;
+            if (own) { Bout[0][o] = bxv; Bout[1][o] = byv; }
+        }
+        if (TE) {
+            const T bzv = Bin[2][o] - (c.tdx * (sE[1][iy][ix + 1] - sE[1][iy][ix]) -
+                                       c.tdy * (sE[0][iy + 1][ix] - sE[0][iy][ix]));
+            sB[2][iy][ix] = bzv;
+            if (own) Bout[2][o] = bzv;
+        }
+    }
+    // x filter of the current rows: (2P + 1) binomial taps
+    if (hasj)
+        for (int e = tid; e < 3 * JY * TX; e += NT) {
+            const int q = e / (JY * TX), r = e % (JY * TX), y = r / TX, x = r % TX;
+            if ((q < 2 && !TE) || (q == 2 && !TM)) continue;
+            T v = T(0);
+            for (int k = -P; k <= P; k++) v = fma(T(binom<P>(k + P)), sJ[q][y][x + P + k], v);
+            sJx[q][y][x] = v;
+        }
+    __syncthreads();
+    double nte = 0.0, ntm = 0.0;
+    for (int e = tid; e < TX * TY; e += NT) {
+        const int y = e / TX, x = e % TX;
+        const int gx = X0 + x, gy = Y0 + y;
+        if (gx >= nx || gy >= ny) continue;
+        // y filter: P cascaded three-tap passes over the x-filtered rows
+        T jf[3] = {T(0), T(0), T(0)};
+        if (hasj)
+            for (int q = 0; q < 3; q++) {
+                if ((q < 2 && !TE) || (q == 2 && !TM)) continue;
+                T w[2 * P + 1];
+                for (int i = 0; i <= 2 * P; i++) w[i] = sJx[q][y + i][x];
+                for (int r = 1; r <= P; r++)
+                    for (int i = 0; i + 2 * r <= 2 * P; i++) w[i] = T(0.25) * fma(T(2), w[i + 1], w[i] + w[i + 2]);
+                jf[q] = w[0];
+            }
+        const int cx = x + 1, cy = y + 1;
+        const size_t o = (size_t)gy * nx + gx;
+        if (TE) {
+            const T vx = c.tdy * (sB[2][cy][cx] - sB[2][cy - 1][cx]) - es * jf[0];
+            const T vy = -c.tdx * (sB[2][cy][cx] - sB[2][cy][cx - 1]) - es * jf[1];
+            a.dEp[0][o] = vx;
+            a.dEp[1][o] = vy;
+            nte += (double)vx * vx + (double)vy * vy;
+        }
+        if (TM) {
+            const T ay = avg6(sB[1][cy - 1][cx], sB[1][cy][cx], sB[1][cy + 1][cx], sixth);
+            const T ayl = avg6(sB[1][cy - 1][cx - 1], sB[1][cy][cx - 1], sB[1][cy + 1][cx - 1], sixth);
+            const T axj = avg6(sB[0][cy][cx - 1], sB[0][cy][cx], sB[0][cy][cx + 1], sixth);
+            const T axm = avg6(sB[0][cy - 1][cx - 1], sB[0][cy - 1][cx], sB[0][cy - 1][cx + 1], sixth);
+            const T vz = c.tdx * (ay - ayl) - c.tdy * (axj - axm) - es * jf[2];
+            a.dEp[2][o] = vz;
+            ntm += (double)vz * vz;
+        }
+    }
+    tile2d::block_sum2(nte, ntm, sred);
+    if (tid == 0) {
+        a.partial[2 * wg] = nte;
+        a.partial[2 * wg + 1] = ntm;
+    }
+}
+
+// sum of the per-workgroup partials, the same in every workgroup
+__device__ __forceinline__ void reduce_partials(const double *partial, int nwg, double *sred, double *sdec,
+                                                double &ra, double &rb)
+{
+    double x = 0.0, y = 0.0;
+    for (int i = threadIdx.x; i < nwg; i += NT) {
+        x += partial[2 * i];
+        y += partial[2 * i + 1];
+    }
+    tile2d::block_sum2(x, y, sred);
+    if (threadIdx.x == 0) { sdec[0] = x; sdec[1] = y; }
+    __syncthreads();
+    ra = sdec[0];
+    rb = sdec[1];
+    __syncthreads();
+}
+
+template <typename T, int BLK, bool DELTA>
+__device__ __forceinline__ void sweep_k(const Coef<T> &c, const SweepArgs<T> &sa, int flags, int k, int bx, int by, int wg,
+                        char *lds, double *sred)
+{
+    constexpr int TX = Tile<T>::TX, TY = Tile<T>::TY;
+    switch (k) {
+    case 1: tile2d::sweep_tile<T, BLK, 1, TX, TY, DELTA>(c, sa, flags, bx, by, wg, lds, sred); break;
+    case 2: tile2d::sweep_tile<T, BLK, 2, TX, TY, DELTA>(c, sa, flags, bx, by, wg, lds, sred); break;
+    case 3: tile2d::sweep_tile<T, BLK, 3, TX, TY, DELTA>(c, sa, flags, bx, by, wg, lds, sred); break;
+    case 4: tile2d::sweep_tile<T, BLK, 4, TX, TY, DELTA>(c, sa, flags, bx, by, wg, lds, sred); break;
+    case 5: tile2d::sweep_tile<T, BLK, 5, TX, TY, DELTA>(c, sa, flags, bx, by, wg, lds, sred); break;
+    case 6: tile2d::sweep_tile<T, BLK, 6, TX, TY, DELTA>(c, sa, flags, bx, by, wg, lds, sred); break;
+    case 7: tile2d::sweep_tile<T, BLK, 7, TX, TY, DELTA>(c, sa, flags, bx, by, wg, lds, sred); break;
+    default: tile2d::sweep_tile<T, BLK, 8, TX, TY, DELTA>(c, sa, flags, bx, by, wg, lds, sred); break;
+    }
+}
+
+template <typename T, bool DELTA>
+__global__ __launch_bounds__(NT) void k2_small(SmallArgs<T> a)
+{
+    __shared__ __attribute__((aligned(16))) char lds[lds_bytes<T>()];
+    __shared__ double sred[2 * NT / 64];
+    __shared__ double sdec[2];
+    __shared__ int sflag;
+    constexpr int TX = Tile<T>::TX, TY = Tile<T>::TY;
+    const Coef<T> &c = a.c;
+    const int nwg = gridDim.x;
+    const int wg = xcd_map(blockIdx.x, nwg);   // tiles x-fastest, neighbours on one XCD
+    const int bx = wg % a.ntx, by = wg / a.ntx;
+    const int nx = c.nx, ny = c.ny;
+    for (int s = 0; s < a.nsteps; s++) {
+        switch (a.filter_passes) {
+        case 0: front<T, 0>(a, s, bx, by, wg, lds, sred); break;
+        case 1: front<T, 1>(a, s, bx, by, wg, lds, sred); break;
+        case 2: front<T, 2>(a, s, bx, by, wg, lds, sred); break;
+        case 3: front<T, 3>(a, s, bx, by, wg, lds, sred); break;
+        default: front<T, 4>(a, s, bx, by, wg, lds, sred); break;
+        }
+        if (!grid_barrier(a.bar, nwg, a.err, &sflag)) return;
+        SmallStat st{};
+        double r0, r1;
+        reduce_partials(a.partial, nwg, sred, sdec, r0, r1);
+        st.rhsn[0] = (a.blocks & 1) ? sqrt(r0) : 0.0;
+        st.rhsn[1] = (a.blocks & 2) ? sqrt(r1) : 0.0;
+        bool active[2];
+        for (int b = 0; b < 2; b++) {
+            if (!isfinite(st.rhsn[b])) st.nonfinite |= 1;
+            // dE' = 0: the increment is 0, no sweeps
+            active[b] = (a.blocks & (1 << b)) && st.rhsn[b] > 0.0 && isfinite(st.rhsn[b]);
+        }
+        int last[2] = {-1, -1}, cur = -1;
+        while (!st.nonfinite && (active[0] || active[1])) {
+            const int b0 = active[0] ? 0 : 1;
+            const int kk = min(a.spp, a.mmax - st.done[b0]);
+            const bool first = st.done[b0] == 0;
+            const int ob = cur == 0 ? 1 : 0;
+            SweepArgs<T> sa{};
+            for (int q = 0; q < 3; q++) {
+                sa.rhs[q] = a.dEp[q];
+                sa.x_in[q] = first ? a.dEp[q] : (cur == 1 ? a.X[1][q] : a.X[0][q]);
+                sa.s_in[q] = a.S[q];
+                sa.x_out[q] = ob == 1 ? a.X[1][q] : a.X[0][q];
+                sa.s_out[q] = a.S[q];
+                sa.E[q] = a.E[q];
+            }
+            sa.partial = a.partial;
+            const int flags = (first ? SW_FIRST : 0) | SW_RESID | SW_STORE;
+            const int act = (active[0] ? 1 : 0) | (active[1] ? 2 : 0);
+            if (act == 1) sweep_k<T, 1, DELTA>(c, sa, flags, kk, bx, by, wg, lds, sred);
+            else if (act == 2) sweep_k<T, 2, DELTA>(c, sa, flags, kk, bx, by, wg, lds, sred);
+            else sweep_k<T, 3, DELTA>(c, sa, flags, kk, bx, by, wg, lds, sred);
+            if (!grid_barrier(a.bar, nwg, a.err, &sflag)) return;
+            reduce_partials(a.partial, nwg, sred, sdec, r0, r1);
+            const double r[2] = {sqrt(r0), sqrt(r1)};
+            for (int b = 0; b < 2; b++) {
+                if (!active[b]) continue;
+                st.done[b] += kk;
+                last[b] = ob;
+                st.resid[b] = r[b];
+                if (!isfinite(r[b])) {
+                    st.nonfinite |= 2;
+                    active[b] = false;
+                } else if (r[b] <= a.tol * st.rhsn[b]) {
+                    st.conv[b] = 1;
+                    active[b] = false;
+                } else if (st.done[b] >= a.mmax) {
+                    active[b] = false;
+                }
+            }
+            cur = ob;
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.stat[s] = st;
+        if (st.nonfinite) return;   // every workgroup took the same decision
+        // E += dE on the own tile
+        for (int e = threadIdx.x; e < TX * TY; e += NT) {
+            const int gx = bx * TX + e % TX, gy = by * TY + e / TX;
+            if (gx >= nx || gy >= ny) continue;
+            const size_t o = (size_t)gy * nx + gx;
+            for (int q = 0; q < 3; q++) {
+                const int b = q == 2 ? 1 : 0;
+                if (st.done[b] == 0) continue;
+                a.E[q][o] += DELTA ? a.S[q][o] : (last[b] == 1 ? a.X[1][q][o] : a.X[0][q][o]);
+            }
+        }
+        if (!grid_barrier(a.bar, nwg, a.err, &sflag)) return;
+    }
+}
+
+}  // namespace small2d
+
+template <typename T>
+void small_tiles(int nx, int ny, int *ntx, int *nty)
+{
+    *ntx = (nx + small2d::Tile<T>::TX - 1) / small2d::Tile<T>::TX;
+    *nty = (ny + small2d::Tile<T>::TY - 1) / small2d::Tile<T>::TY;
+}
+
+template <typename T>
+int small_capacity(bool delta)
+{
+    static std::atomic<int> cache[2][MX_MAX_DEVICES];
+    return per_device(cache[delta ? 1 : 0], [&]() {
+        int dev = 0, coop = 0, cu = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return 0;
+        if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+        const void *k = delta ? (const void *)small2d::k2_small<T, true> : (const void *)small2d::k2_small<T, false>;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, small2d::NT, 0) != hipSuccess) return 0;
+        return per * cu;
+    });
+}
+
+template <typename T>
+hipError_t launch_small(const SmallArgs<T> &a, bool delta, hipStream_t s)
+{
+    void *args[] = {(void *)&a};
+    const int nwg = a.ntx * a.nty;
+    const void *k = delta ? (const void *)small2d::k2_small<T, true> : (const void *)small2d::k2_small<T, false>;
+    return hipLaunchCooperativeKernel(k, dim3(nwg), dim3(small2d::NT), args, 0, s);
+}
+
+}  // namespace mx

@@ -107,6 +107,13 @@ int stream_workgroups(const mx_config *c, int variant, int ncu)
     return (int)std::min(nsx * nsy, 0x7fffffffLL);
 }
 
+// workspace of the single-launch small-grid solve: per-step current
+// factors and records, barrier counters and flag
+size_t small_area()
+{
+    return up(SMALL_MAX_STEPS * sizeof(double)) + up(SMALL_MAX_STEPS * sizeof(SmallStat)) + up(4 * sizeof(unsigned));
+}
+
 // number of full-grid arrays in the workspace
 int n_arrays(const mx_config *c)
 {
@@ -143,6 +150,13 @@ struct mx_grid {
     double *red;          // device, 2 doubles
     double *hred = nullptr;   // pinned host memory for read-backs (a TolState)
     TolState hbuf;            // pageable read-back target when hred is not set
+    // single-launch small-grid solve: device areas in the workspace, and
+    // pageable host copies (the per-step records and current factors)
+    void *small_env;
+    SmallStat *small_stat;
+    unsigned *small_bar;      // [0..2] barrier, [3] time-out flag
+    SmallStat hstat[SMALL_MAX_STEPS];
+    double henv[SMALL_MAX_STEPS];
     TolState *tol;        // device: the tolerance solve's state within a step
     int spec[2] = {1, 1}; // passes per block the last tolerance solve ran (queued ahead next step)
     int spp[2];           // sweeps per pass of the TE and TM blocks (3D: [0])
@@ -324,6 +338,17 @@ static void grid_setup(mx_grid *g, const mx_config *cfg, hipStream_t stream, int
     g->red = (double *)p;
     p += up(8 * sizeof(double));
     g->tol = (TolState *)p;
+    p += up(sizeof(TolState));
+    g->small_env = nullptr;
+    g->small_stat = nullptr;
+    g->small_bar = nullptr;
+    if (cfg->ndim == 2) {
+        g->small_env = p;
+        p += up(SMALL_MAX_STEPS * sizeof(double));
+        g->small_stat = (SmallStat *)p;
+        p += up(SMALL_MAX_STEPS * sizeof(SmallStat));
+        g->small_bar = (unsigned *)p;
+    }
     for (int q = 0; q < 3; q++) { g->E[q] = g->B[q] = g->J0[q] = nullptr; g->bloc[q] = 0; }
     fill_coef(cfg, g->cf);
     fill_coef(cfg, g->cd);
@@ -376,10 +401,10 @@ int mx_validate(const mx_config *c, int *warn)
     if (c->solver == MX_SOLVER_CHEBYSHEV) {
         if (c->ndim == 3 && !(c->d[0] == c->d[1] && c->d[1] == c->d[2]))
             return fail(MX_EINVAL, "the 3D Chebyshev solve is defined for cubic cells");
-        if (c->ndim == 3 && c->sweeps_per_pass > 1)
-            return fail(MX_EINVAL, "the 3D Chebyshev solve runs one sweep per pass");
         if (c->variant == 1) return fail(MX_EINVAL, "the Chebyshev solve runs on the row-streaming kernels (variant 0, 2 or 3)");
         if (c->form != MX_FORM_STANDARD) return fail(MX_EINVAL, "the Chebyshev solve uses the standard form");
+        if (c->ndim == 3 && c->sweeps_per_pass > 1)
+            return fail(MX_EINVAL, "the 3D Chebyshev solve runs one sweep per pass");
         if (c->lumped) return fail(MX_EINVAL, "the lumped scheme has A = 0: no solve to accelerate");
     }
     if (c->sweeps_per_pass < 0 || c->sweeps_per_pass > 16) return fail(MX_EINVAL, "sweeps_per_pass must be in [0, 16]");
@@ -408,7 +433,7 @@ int mx_workspace_size(const mx_config *c, size_t *bytes)
     if (!bytes) return fail(MX_EINVAL, "bytes is NULL");
     const size_t arr = up((size_t)ncell_of(c) * elem_of(c));
     *bytes = n_arrays(c) * arr + up((size_t)max_wg(c) * 2 * sizeof(double)) + up(8 * sizeof(double)) +
-             up(sizeof(TolState));
+             up(sizeof(TolState)) + (c->ndim == 2 ? small_area() : 0);
     return MX_OK;
 }
 
@@ -433,9 +458,10 @@ int mx_init(const mx_config *cfg, void *stream, void *workspace, size_t workspac
     grid_setup(g, cfg, (hipStream_t)stream, attr.device, (char *)workspace, workspace_bytes);
     // pinned host memory: the tolerance solve reads its state back by DMA
     // rather than through a staged pageable copy
-    if (hipHostMalloc((void **)&g->hred, sizeof(TolState), hipHostMallocDefault) != hipSuccess) {
+    const size_t hbytes = std::max(sizeof(TolState), SMALL_MAX_STEPS * (sizeof(SmallStat) + sizeof(double)));
+    if (hipHostMalloc((void **)&g->hred, hbytes, hipHostMallocDefault) != hipSuccess) {
         delete g;
-        return fail(MX_EDEVICE, "pinned host buffer of %zu bytes could not be allocated", sizeof(TolState));
+        return fail(MX_EDEVICE, "pinned host buffer of %zu bytes could not be allocated", hbytes);
     }
     *out = g;
     return MX_OK;
@@ -806,6 +832,95 @@ int run_sweeps(mx_grid *g, void *const rhs[3], const int *target_in, bool tolmod
     return MX_OK;
 }
 
+// The single-launch solve applies to 2D tolerance solves (Alg 1) on the
+// LDS-tile kernel (grids too small for row streams) whose tiles fit the
+// co-resident workgroups of one cooperative launch.
+template <typename T>
+bool small_ok(const mx_grid *g)
+{
+    const mx_config &c = g->cfg;
+    if (c.ndim != 2 || !(c.tol > 0.0) || g->variant != 1 || c.solver != MX_SOLVER_ALG1 || c.lumped) return false;
+    if (c.filter_passes > 4 || g->spp[0] < 1 || g->spp[0] > 8 || c.sweeps < 1 || !g->small_bar) return false;
+    int ntx = 0, nty = 0;
+    small_tiles<T>((int)c.n[0], (int)c.n[1], &ntx, &nty);
+    return (long long)ntx * nty <= small_capacity<T>(c.form == MX_FORM_DELTA) && (long long)ntx * nty <= max_wg(&c);
+}
+
+template <typename T>
+int small_steps(mx_grid *g, int nsteps, const double *env, mx_step_stats *stats)
+{
+    const mx_config &c = g->cfg;
+    const bool delta = c.form == MX_FORM_DELTA;
+    SmallArgs<T> a{};
+    a.c = coef<T>(g);
+    for (int q = 0; q < 3; q++) {
+        a.E[q] = (T *)g->E[q];
+        a.B[0][q] = (T *)(g->bloc[q] ? g->Bws[q] : g->B[q]);
+        a.B[1][q] = (T *)(g->bloc[q] ? g->B[q] : g->Bws[q]);
+        a.J0[q] = g->has_j ? (const T *)g->J0[q] : nullptr;
+        a.dEp[q] = (T *)g->dEp[q];
+        a.X[0][q] = (T *)g->X[0][q];
+        a.X[1][q] = (T *)g->X[1][q];
+        a.S[q] = (T *)g->S[q];
+    }
+    a.partial = g->partial;
+    a.bar = g->small_bar;
+    a.err = (int *)(g->small_bar + 3);
+    a.stat = g->small_stat;
+    a.env_src = (const T *)g->small_env;
+    a.tol = c.tol;
+    a.blocks = c.blocks;
+    a.spp = g->spp[0];
+    a.mmax = c.sweeps;
+    a.filter_passes = g->has_j ? c.filter_passes : 0;
+    small_tiles<T>((int)c.n[0], (int)c.n[1], &a.ntx, &a.nty);
+    // host staging: the pinned buffer of mx_init grids, else the grid's own
+    SmallStat *hs = g->hred ? (SmallStat *)g->hred : g->hstat;
+    T *he = g->hred ? (T *)((char *)g->hred + SMALL_MAX_STEPS * sizeof(SmallStat)) : (T *)g->henv;
+    static const unsigned zero[4] = {0, 0, 0, 0};
+    for (int s0 = 0; s0 < nsteps; s0 += SMALL_MAX_STEPS) {
+        const int n = std::min(SMALL_MAX_STEPS, nsteps - s0);
+        for (int i = 0; i < n; i++) he[i] = (T)((env ? env[s0 + i] : 0.0) * c.four_pi * c.dt);
+        HIPCHK(hipMemcpyAsync(g->small_env, he, n * sizeof(T), hipMemcpyHostToDevice, g->stream));
+        HIPCHK(hipMemcpyAsync(g->small_bar, zero, 4 * sizeof(unsigned), hipMemcpyHostToDevice, g->stream));
+        a.nsteps = n;
+        {
+            ProfScope ps(g, MX_PROF_SWEEP, 0.0);
+            HIPCHK(launch_small<T>(a, delta, g->stream));
+        }
+        HIPCHK(hipMemcpyAsync(hs, g->small_stat, n * sizeof(SmallStat), hipMemcpyDeviceToHost, g->stream));
+        unsigned flag[4];
+        HIPCHK(hipMemcpyAsync(flag, g->small_bar, 4 * sizeof(unsigned), hipMemcpyDeviceToHost, g->stream));
+        HIPCHK(hipStreamSynchronize(g->stream));
+        if (flag[3]) return fail(MX_EDEVICE, "single-launch tolerance solve: grid barrier timed out");
+        for (int i = 0; i < n; i++) {
+            if (hs[i].nonfinite & 1)
+                return fail(MX_ENONFINITE, "step %lld: norm of dE' is not finite", (long long)(g->step + i));
+            if (hs[i].nonfinite & 2)
+                return fail(MX_ENONFINITE, "step %lld: a residual norm is not finite", (long long)(g->step + i));
+            if (stats) {
+                mx_step_stats &st = stats[s0 + i];
+                for (int b = 0; b < 2; b++) {
+                    st.sweeps[b] = hs[i].done[b];
+                    st.resid[b] = hs[i].resid[b];
+                    st.rhs[b] = hs[i].rhsn[b];
+                    st.nonconverged[b] = (c.blocks & (1 << b)) && hs[i].done[b] > 0 && !hs[i].conv[b] ? 1 : 0;
+                }
+            }
+        }
+        // B of the active blocks moved to the other buffer after an odd count
+        if (n & 1)
+            for (int q = 0; q < 3; q++) {
+                const bool act = q == 2 ? (c.blocks & 1) : (c.blocks & 2);
+                if (!act) continue;
+                std::swap(a.B[0][q], a.B[1][q]);
+                g->bloc[q] ^= 1;
+            }
+        g->step += n;
+    }
+    return MX_OK;
+}
+
 template <typename T>
 int step_impl(mx_grid *g, int nsteps, const double *env, const int *replay, mx_step_stats *stats)
 {
@@ -813,6 +928,11 @@ int step_impl(mx_grid *g, int nsteps, const double *env, const int *replay, mx_s
     const Coef<T> &k = coef<T>(g);
     const int nblk = c.ndim == 3 ? 1 : 2;
     const bool tolmode = c.tol > 0.0 && replay == nullptr;
+    if (tolmode && nsteps > 0 && small_ok<T>(g)) {
+        const int rc = small_steps<T>(g, nsteps, env, stats);
+        if (rc) return rc;
+        nsteps = 0;   // done; the hand-back below returns B to the caller's buffers
+    }
     for (int s = 0; s < nsteps; s++) {
         const double e = env ? env[s] : 0.0;
         const T env_src = (T)(e * c.four_pi * c.dt);

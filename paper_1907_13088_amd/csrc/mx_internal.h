@@ -218,6 +218,45 @@ int step_on_scratch(const mx_config *cfg, void *stream, int device, void *ws, si
                     void *const B[3], void *const J0[3], int nsteps, const double *env, const int *replay,
                     mx_step_stats *stats);
 
+// Single-launch tolerance solve of small 2D grids (k2small_impl.h): all
+// passes of up to SMALL_MAX_STEPS steps in one cooperative launch, the stop
+// test on the device, one read-back of the per-step records per launch.
+constexpr int SMALL_MAX_STEPS = 64;
+struct SmallStat {
+    int done[2];          // sweeps per block (TE, TM)
+    int conv[2];          // met the tolerance
+    double resid[2];      // last step norm per block
+    double rhsn[2];       // ||dE'|| per block
+    int nonfinite;        // bit 0: ||dE'||, bit 1: a residual
+    int pad;
+};
+template <typename T>
+struct SmallArgs {
+    Coef<T> c;
+    T *E[3];
+    T *B[2][3];           // step s reads B[s & 1][q], writes B[(s + 1) & 1][q] (active blocks)
+    const T *J0[3];       // null: no current
+    T *dEp[3];
+    T *X[2][3];
+    T *S[3];              // running sum (delta form)
+    double *partial;      // per-workgroup FP64 partial norms [workgroups][2]
+    unsigned *bar;        // grid barrier counters, zero at launch
+    int *err;             // barrier time-out flag, zero at launch
+    SmallStat *stat;      // [nsteps]
+    const T *env_src;     // [nsteps] env * 4 pi dt of each step (device)
+    double tol;
+    int nsteps, blocks, spp, mmax, filter_passes;
+    int ntx, nty;         // tiles per axis
+};
+// tiles of the grid (workgroups of the launch) and the co-resident limit of
+// the kernel on the current device (0: no cooperative launch)
+template <typename T>
+void small_tiles(int nx, int ny, int *ntx, int *nty);
+template <typename T>
+int small_capacity(bool delta);
+template <typename T>
+hipError_t launch_small(const SmallArgs<T> &a, bool delta, hipStream_t s);
+
 // Particle push and charge-conserving deposition, 2D (kpic.hip)
 template <typename T>
 struct PicArgs {
