@@ -92,12 +92,8 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(3)
 
-    if args.workload != "modes2d":
-        steps = args.steps if "--steps" in sys.argv else None
-        warm = args.warmup if "--warmup" in sys.argv else None
-        print(json.dumps(OTHER_WORKLOADS[args.workload](steps, warm)), flush=True)
-        return
-
+    global SPP
+    SPP = args.spp
     if args.copy_probe > 0:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
         # calibrate the HBM traffic read for the field kernels
@@ -108,6 +104,12 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: 4 x {args.copy_probe} bytes")
         del src, dst
+
+    if args.workload != "modes2d":
+        steps = args.steps if "--steps" in sys.argv else None
+        warm = args.warmup if "--warmup" in sys.argv else None
+        print(json.dumps(OTHER_WORKLOADS[args.workload](steps, warm)), flush=True)
+        return
 
     K, W = args.steps, args.warmup
     n = args.n
@@ -324,6 +326,9 @@ def main():
 # The other workloads (not the headline line): each prints one JSON object
 # --------------------------------------------------------------------------
 
+SPP = 0   # sweeps per pass of the other workloads' grids (0: library choice), from --spp
+
+
 def _events():
     import torch
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -345,7 +350,7 @@ def bench_planewave_te(steps, warm):
     # varies twofold with the GPU clock ramping up
     steps = steps or 1000
     w = I.planewave_te_2d(steps=steps)
-    cfg = mx.make_config(2, w.shape[::-1], w.dt, w.d, "f64", w.blocks, w.sweeps, w.tol, 0)
+    cfg = mx.make_config(2, w.shape[::-1], w.dt, w.d, "f64", w.blocks, w.sweeps, w.tol, 0, sweeps_per_pass=SPP)
     g = mx.Grid(cfg)
     E = [torch.tensor(a, device="cuda") for a in w.E]
     B = [torch.tensor(a, device="cuda") for a in w.B]
@@ -360,7 +365,7 @@ def bench_planewave_te(steps, warm):
     return _line("128x128 TE plane wave, FP64, tol 1e-12", w.cells * steps / dt / 1e9, "Gcell-steps/s",
                  {"steps": steps, "us_per_step": round(dt / steps * 1e6, 1), "mean_sweeps": round(sweeps, 1),
                   "sweeps_per_pass": g.sweeps_per_pass, "dtype": "f64",
-                  "note": "latency bound: tiny kernels; the stop test runs on the device, one host read-back per step"})
+                  "note": "latency bound: one cooperative launch runs up to 64 steps, the stop test on the device"})
 
 
 def _run_3d(steps, warm, solver, form):
@@ -373,7 +378,7 @@ def _run_3d(steps, warm, solver, form):
     w = I.planewave_3d(steps=steps + warm)
     log(f"3D inputs generated in {time.time() - t0:.1f}s")
     cfg = mx.make_config(3, w.shape[::-1], w.dt, w.d, "f32", 3, w.sweeps, w.tol, w.filter_passes,
-                         form=form, solver=solver)
+                         form=form, solver=solver, sweeps_per_pass=SPP)
     g = mx.Grid(cfg)
     E = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in w.E]
     B = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in w.B]
@@ -391,6 +396,7 @@ def _run_3d(steps, warm, solver, form):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = g.profile_read()
+    g_spp = g.sweeps_per_pass
     g.close()
     del E, B, J
     torch.cuda.empty_cache()
@@ -398,6 +404,7 @@ def _run_3d(steps, warm, solver, form):
     sweeps = sum(s.sweeps[0] for s in st) / steps
     return w.cells * steps / dt / 1e9, {
         "steps": steps, "ms_per_step": round(dt / steps * 1e3, 2), "mean_sweeps": round(sweeps, 1),
+        "sweeps_per_pass": g_spp,
         "nonconverged_steps": sum(s.nonconverged[0] for s in st),
         "sweep_pass_us": round(1e3 * sw["ms"] / max(sw["launches"], 1), 1),
         "sweep_pass_GBps": round(sw["bytes"] / (sw["ms"] / 1e3) / 1e9, 1) if sw["ms"] else None}

@@ -79,9 +79,9 @@ extern "C" {
    and its tolerance test uses the same residual ||dE' + A x - x||_2, but
    its iterates differ: it reaches a given residual in far fewer sweeps.
    2D row streaming (variants 0, 2, 3) or 3D with cubic cells (where 1 - A
-   spans [1/9, 1]) at one sweep per pass; standard form, not lumped; not in
-   a batch.  Its result after m sweeps is a polynomial in A applied to
-   dE', so mx_adjoint transposes it with the same kernels. */
+   spans [1/9, 1]); standard form, not lumped; not in a batch.  Its result
+   after m sweeps is a polynomial in A applied to dE', so mx_adjoint
+   transposes it with the same kernels. */
 #define MX_SOLVER_ALG1      0
 #define MX_SOLVER_CHEBYSHEV 1
 
@@ -109,7 +109,8 @@ typedef struct mx_config {
                              kernel built: both blocks together 7 (FP32), 3 (FP64),
                              delta form 6, 3; per block TE 10 (FP32), 5 (FP64),
                              delta 9, 4; TM 16 (FP32), 8 (FP64).  LDS tile: <= 8.
-                             3D: 1 (library choice) or 2 in FP32, 1 in FP64. */
+                             3D: up to 3 in FP32, 2 in FP64 (library choice: the
+                             most allowed). */
     int variant;          /* 2D sweep kernel: 0 library choice (FP32: 2, FP64 and
                              the Chebyshev solve: 3; Alg 1 on a grid whose
                              streaming pass would have fewer workgroups than
@@ -120,7 +121,7 @@ typedef struct mx_config {
                              (both blocks per pass), 3 row streaming (each block
                              on its own) */
     int solver;           /* MX_SOLVER_ALG1 (default) or MX_SOLVER_CHEBYSHEV (2D,
-                             and 3D with cubic cells at one sweep per pass); the
+                             and 3D with cubic cells); the
                              2D Chebyshev passes fuse at most: both blocks 5
                              (FP32), 2 (FP64); TE 8, 3; TM 12, 6 */
 } mx_config;
@@ -177,6 +178,9 @@ int mx_set_current(mx_grid *g, void *const J0[3]);
    once per step to read the outcome; a non-finite norm is reported at
    that read. */
 int mx_step(mx_grid *g, int nsteps, const double *env, const int *replay, mx_step_stats *stats);
+/* (With the environment variable MX_STATS set, mx_step also writes each
+   step's record as one JSON line: MX_STATS=1 to stderr, any other value
+   names a file the lines are appended to; "0" or empty: off.) */
 
 /* Step counter n of the bound state. */
 int mx_get_step(mx_grid *g, int64_t *n);
@@ -327,8 +331,12 @@ int mx_sources_project(mx_grid *g, int nsrc, int W, const int64_t *origins, cons
  * first config deep (capped at 7); mx_batch_init with sweeps_per_pass = 0
  * times candidate pass depths and chunk lengths on workspace scratch
  * fields (the bound state is never touched), separately for the grouped
- * and the persistent schedule, and keeps the fastest of each.  The
- * workspace holds 15 arrays per grid.
+ * and the persistent schedule, and keeps the fastest of each.  The chosen
+ * plans are kept in a text file and reused by a later init of the same
+ * grid configs on the same device and library build: $MX_TUNE_CACHE (a
+ * path; "0" or empty turns the cache off), else
+ * $XDG_CACHE_HOME/mx/batch_plans.txt or $HOME/.cache/mx/batch_plans.txt.
+ * The workspace holds 15 arrays per grid.
  * ------------------------------------------------------------------------ */
 typedef struct mx_batch mx_batch;
 

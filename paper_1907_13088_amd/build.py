@@ -19,7 +19,7 @@ SOURCES = ["k2small_f64.hip", "k2small_f32.hip", "k2s_f32_tm.hip", "k2s_f32d_tm.
            "k2s_f32d_all.hip", "k2s_f64_tm.hip", "k2s_f64d_tm.hip", "k2s_f64_te.hip", "k2s_f64d_te.hip",
            "k2s_f64_all.hip", "k2s_f64d_all.hip", "k2s_f32c_te.hip", "k2s_f32c_tm.hip", "k2s_f32c_all.hip",
            "k2s_f64c_te.hip", "k2s_f64c_tm.hip", "k2s_f64c_all.hip", "k2d.hip", "k2f.hip", "kbatch_f32.hip", "kbatch_f64.hip",
-           "k3d.hip", "k3f.hip", "kpic.hip", "kadj.hip", "k2s.hip", "mx_api.cpp", "mx_batch.cpp", "mx_static.hip"]
+           "k3s.hip", "k3d.hip", "k3f.hip", "kpic.hip", "kadj.hip", "k2s.hip", "mx_api.cpp", "mx_batch.cpp", "mx_static.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # packed FP32 VALU forms stay off: plain FP32 VALU only

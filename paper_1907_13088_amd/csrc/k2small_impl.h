@@ -61,8 +61,11 @@ __device__ __forceinline__ T avg6(T fm, T f0, T fp, T sixth)
 // The front of step s on tile (bx, by): B^{n+1/2} on the tile and a
 // one-cell halo, dE' on the tile, its FP64 norm per block in partial[wg].
 // The arithmetic of each output is that of the streaming front kernel.
+// inc[q] (null: none) is the previous step's increment of E component q,
+// not yet added to E in memory: E^n = E + inc, formed as the E update forms it.
 template <typename T, int P>
-__device__ __forceinline__ void front(const SmallArgs<T> &a, int s, int bx, int by, int wg, char *lds, double *sred)
+__device__ __forceinline__ void front(const SmallArgs<T> &a, int s, int bx, int by, int wg, char *lds, double *sred,
+                                      const T *const inc[3])
 {
     constexpr int TX = Tile<T>::TX, TY = Tile<T>::TY;
     constexpr int EX = TX + 3, EY = TY + 3, BX = TX + 2, BY = TY + 2, JX = TX + 2 * P, JY = TY + 2 * P;
@@ -88,7 +91,9 @@ __device__ __forceinline__ void front(const SmallArgs<T> &a, int s, int bx, int 
     for (int e = tid; e < 3 * EY * EX; e += NT) {
         const int q = e / (EY * EX), r = e % (EY * EX), iy = r / EX, ix = r % EX;
         if ((q < 2 && !TE) || (q == 2 && !TM)) continue;
-        sE[q][iy][ix] = a.E[q][(size_t)wrapi(Y0 - 1 + iy, ny) * nx + wrapi(X0 - 1 + ix, nx)];
+        const size_t o = (size_t)wrapi(Y0 - 1 + iy, ny) * nx + wrapi(X0 - 1 + ix, nx);
+        const T *iq = q == 0 ? inc[0] : (q == 1 ? inc[1] : inc[2]);
+        sE[q][iy][ix] = iq ? a.E[q][o] + iq[o] : a.E[q][o];
     }
     if (hasj)
         for (int e = tid; e < 3 * JY * JX; e += NT) {
@@ -205,6 +210,28 @@ __device__ __forceinline__ void sweep_k(const Coef<T> &c, const SweepArgs<T> &sa
     }
 }
 
+// E += inc on the own tile (inc[q] null: component unchanged)
+template <typename T>
+__device__ __forceinline__ void add_increment(const SmallArgs<T> &a, int bx, int by, const T *const inc[3])
+{
+    constexpr int TX = Tile<T>::TX, TY = Tile<T>::TY;
+    const int nx = a.c.nx, ny = a.c.ny;
+    for (int e = threadIdx.x; e < TX * TY; e += NT) {
+        const int gx = bx * TX + e % TX, gy = by * TY + e / TX;
+        if (gx >= nx || gy >= ny) continue;
+        const size_t o = (size_t)gy * nx + gx;
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            const T *iq = q == 0 ? inc[0] : (q == 1 ? inc[1] : inc[2]);
+            if (iq) a.E[q][o] += iq[o];
+        }
+    }
+}
+
+// A step's E increment is added to E in memory after the next step's front
+// has read E (the front adds it on the fly for its tile and halo), right
+// after the barrier that ends that front and before the first sweep pass
+// can overwrite the iterate: no barrier of its own.
 template <typename T, bool DELTA>
 __global__ __launch_bounds__(NT) void k2_small(SmallArgs<T> a)
 {
@@ -212,21 +239,21 @@ __global__ __launch_bounds__(NT) void k2_small(SmallArgs<T> a)
     __shared__ double sred[2 * NT / 64];
     __shared__ double sdec[2];
     __shared__ int sflag;
-    constexpr int TX = Tile<T>::TX, TY = Tile<T>::TY;
     const Coef<T> &c = a.c;
     const int nwg = gridDim.x;
     const int wg = xcd_map(blockIdx.x, nwg);   // tiles x-fastest, neighbours on one XCD
     const int bx = wg % a.ntx, by = wg / a.ntx;
-    const int nx = c.nx, ny = c.ny;
+    const T *inc[3] = {nullptr, nullptr, nullptr};   // the previous step's E increment
     for (int s = 0; s < a.nsteps; s++) {
         switch (a.filter_passes) {
-        case 0: front<T, 0>(a, s, bx, by, wg, lds, sred); break;
-        case 1: front<T, 1>(a, s, bx, by, wg, lds, sred); break;
-        case 2: front<T, 2>(a, s, bx, by, wg, lds, sred); break;
-        case 3: front<T, 3>(a, s, bx, by, wg, lds, sred); break;
-        default: front<T, 4>(a, s, bx, by, wg, lds, sred); break;
+        case 0: front<T, 0>(a, s, bx, by, wg, lds, sred, inc); break;
+        case 1: front<T, 1>(a, s, bx, by, wg, lds, sred, inc); break;
+        case 2: front<T, 2>(a, s, bx, by, wg, lds, sred, inc); break;
+        case 3: front<T, 3>(a, s, bx, by, wg, lds, sred, inc); break;
+        default: front<T, 4>(a, s, bx, by, wg, lds, sred, inc); break;
         }
         if (!grid_barrier(a.bar, nwg, a.err, &sflag)) return;
+        add_increment(a, bx, by, inc);
         SmallStat st{};
         double r0, r1;
         reduce_partials(a.partial, nwg, sred, sdec, r0, r1);
@@ -281,19 +308,20 @@ __global__ __launch_bounds__(NT) void k2_small(SmallArgs<T> a)
         }
         if (blockIdx.x == 0 && threadIdx.x == 0) a.stat[s] = st;
         if (st.nonfinite) return;   // every workgroup took the same decision
-        // E += dE on the own tile
-        for (int e = threadIdx.x; e < TX * TY; e += NT) {
-            const int gx = bx * TX + e % TX, gy = by * TY + e / TX;
-            if (gx >= nx || gy >= ny) continue;
-            const size_t o = (size_t)gy * nx + gx;
-            for (int q = 0; q < 3; q++) {
-                const int b = q == 2 ? 1 : 0;
-                if (st.done[b] == 0) continue;
-                a.E[q][o] += DELTA ? a.S[q][o] : (last[b] == 1 ? a.X[1][q][o] : a.X[0][q][o]);
-            }
+        // this step's increment: dE = S (delta form) or the last iterate
+        for (int q = 0; q < 3; q++) {
+            const int b = q == 2 ? 1 : 0;
+            const T *d = st.done[b] == 0 ? nullptr
+                         : DELTA         ? (q == 0 ? a.S[0] : (q == 1 ? a.S[1] : a.S[2]))
+                         : last[b] == 1  ? (q == 0 ? a.X[1][0] : (q == 1 ? a.X[1][1] : a.X[1][2]))
+                                         : (q == 0 ? a.X[0][0] : (q == 1 ? a.X[0][1] : a.X[0][2]));
+            if (q == 0) inc[0] = d;
+            else if (q == 1) inc[1] = d;
+            else inc[2] = d;
         }
-        if (!grid_barrier(a.bar, nwg, a.err, &sflag)) return;
     }
+    // the last step's increment (no front follows within this launch)
+    add_increment(a, bx, by, inc);
 }
 
 }  // namespace small2d

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -62,11 +63,10 @@ int64_t max_wg(const mx_config *c)
 void pass_depths(const mx_config *c, int variant, int out[2])
 {
     if (c->ndim == 3) {
-        // 3D: one sweep per pass by default; FP32 may ask for two (the
-        // two-level z-marching kernel, measured slower on 512^3: its tile
-        // spends a third of its lanes on halo cells)
-        const int kmax = c->dtype == MX_F64 ? 1 : 2;
-        out[0] = out[1] = c->sweeps_per_pass > 0 ? std::min(c->sweeps_per_pass, kmax) : 1;
+        // 3D: z-marching passes of up to three sweeps (FP32; two in FP64),
+        // as deep as allowed by default
+        const int kmax = mx::stream3d_kmax(c->dtype == MX_F64);
+        out[0] = out[1] = c->sweeps_per_pass > 0 ? std::min(c->sweeps_per_pass, kmax) : kmax;
         return;
     }
     const bool f64 = c->dtype == MX_F64;
@@ -403,16 +403,14 @@ int mx_validate(const mx_config *c, int *warn)
             return fail(MX_EINVAL, "the 3D Chebyshev solve is defined for cubic cells");
         if (c->variant == 1) return fail(MX_EINVAL, "the Chebyshev solve runs on the row-streaming kernels (variant 0, 2 or 3)");
         if (c->form != MX_FORM_STANDARD) return fail(MX_EINVAL, "the Chebyshev solve uses the standard form");
-        if (c->ndim == 3 && c->sweeps_per_pass > 1)
-            return fail(MX_EINVAL, "the 3D Chebyshev solve runs one sweep per pass");
         if (c->lumped) return fail(MX_EINVAL, "the lumped scheme has A = 0: no solve to accelerate");
     }
     if (c->sweeps_per_pass < 0 || c->sweeps_per_pass > 16) return fail(MX_EINVAL, "sweeps_per_pass must be in [0, 16]");
     if (c->variant < 0 || c->variant > 3) return fail(MX_EINVAL, "variant must be 0, 1, 2 or 3");
     if (c->variant == 1 && c->sweeps_per_pass > 8)
         return fail(MX_EINVAL, "the LDS-tile kernel runs at most 8 sweeps per pass");
-    if (c->ndim == 3 && c->sweeps_per_pass > (c->dtype == MX_F64 ? 1 : 2))
-        return fail(MX_EINVAL, "3D grids run at most two sweeps per pass in FP32, one in FP64");
+    if (c->ndim == 3 && c->sweeps_per_pass > mx::stream3d_kmax(c->dtype == MX_F64))
+        return fail(MX_EINVAL, "3D grids run at most three sweeps per pass in FP32, two in FP64");
     if (!(c->dt > 0.0) || !std::isfinite(c->dt)) return fail(MX_EINVAL, "dt must be positive and finite");
     double s = 0.0;
     for (int a = 0; a < c->ndim; a++) s += 1.0 / (c->d[a] * c->d[a]);
@@ -1116,8 +1114,35 @@ int mx_step(mx_grid *g, int nsteps, const double *env, const int *replay, mx_ste
     if (!g->bound) return fail(MX_ESTATE, "mx_step before mx_bind_fields");
     if (nsteps < 0) return fail(MX_EINVAL, "nsteps must be >= 0");
     HIPCHK(hipSetDevice(g->device));
-    return g->cfg.dtype == MX_F64 ? step_impl<double>(g, nsteps, env, replay, stats)
-                                  : step_impl<float>(g, nsteps, env, replay, stats);
+    auto run = [&](mx_step_stats *st) {
+        return g->cfg.dtype == MX_F64 ? step_impl<double>(g, nsteps, env, replay, st)
+                                      : step_impl<float>(g, nsteps, env, replay, st);
+    };
+    const char *dump = std::getenv("MX_STATS");
+    if (!dump || !*dump || std::strcmp(dump, "0") == 0) return run(stats);
+    // per-step records as JSON lines: MX_STATS=1 writes them to stderr, any
+    // other value names a file they are appended to
+    std::vector<mx_step_stats> rec((size_t)nsteps);
+    const int64_t s0 = g->step;
+    const int rc = run(rec.data());
+    const int done = (int)std::min<int64_t>(nsteps, g->step - s0);
+    if (stats) std::copy(rec.begin(), rec.begin() + done, stats);
+    FILE *f = std::strcmp(dump, "1") == 0 ? stderr : std::fopen(dump, "a");
+    if (f) {
+        const mx_config &c = g->cfg;
+        for (int s = 0; s < done; s++) {
+            const mx_step_stats &r = rec[s];
+            std::fprintf(f,
+                         "{\"grid\": \"%p\", \"step\": %lld, \"ndim\": %d, \"n\": [%lld, %lld, %lld], "
+                         "\"tol\": %.6g, \"sweeps\": [%d, %d], \"resid\": [%.17g, %.17g], \"rhs\": [%.17g, %.17g], "
+                         "\"nonconverged\": [%d, %d]}\n",
+                         (void *)g, (long long)(s0 + s), c.ndim, (long long)c.n[0], (long long)c.n[1],
+                         (long long)(c.ndim == 3 ? c.n[2] : 1), c.tol, r.sweeps[0], r.sweeps[1], r.resid[0],
+                         r.resid[1], r.rhs[0], r.rhs[1], r.nonconverged[0], r.nonconverged[1]);
+        }
+        if (f != stderr) std::fclose(f);
+    }
+    return rc;
 }
 
 }  // extern "C"

@@ -2,10 +2,13 @@
 // validation, workspace carving, device descriptors, the grouped and the
 // persistent schedules, and the autotuner for sweeps per pass and chunk
 // length.
+#include <sys/stat.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -346,6 +349,84 @@ int autotune(mx_batch *b, bool grouped, bool persistent)
     return MX_OK;
 }
 
+// Tuned schedules are kept on disk, one line per batch shape:
+//   <key> <spp> <Lf> <Ls> <pk> <pLf> <pLs>
+// The key hashes the grid configs (sizes, cells, dt, dtype, m), the device
+// (architecture name, compute units) and this library's build, so a plan
+// is reused only where it was measured.  The file is $MX_TUNE_CACHE when
+// set ("0" or empty: no cache), else $XDG_CACHE_HOME/mx/batch_plans.txt or
+// $HOME/.cache/mx/batch_plans.txt.  A missing or unreadable file only
+// means the autotuner runs.
+std::string tune_cache_path()
+{
+    const char *e = std::getenv("MX_TUNE_CACHE");
+    if (e) return (e[0] == '\0' || std::strcmp(e, "0") == 0) ? std::string() : std::string(e);
+    std::string dir;
+    if (const char *x = std::getenv("XDG_CACHE_HOME")) dir = x;
+    else if (const char *h = std::getenv("HOME")) dir = std::string(h) + "/.cache";
+    else return std::string();
+    dir += "/mx";
+    (void)mkdir(dir.c_str(), 0755);
+    return dir + "/batch_plans.txt";
+}
+
+uint64_t tune_key(const mx_batch *b)
+{
+    uint64_t h = 1469598103934665603ULL;   // FNV-1a
+    auto mix = [&](const void *p, size_t n) {
+        for (size_t i = 0; i < n; i++) { h ^= ((const unsigned char *)p)[i]; h *= 1099511628211ULL; }
+    };
+    const char *build = __DATE__ " " __TIME__;
+    mix(build, std::strlen(build));
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) {
+        mix(prop.gcnArchName, std::strlen(prop.gcnArchName));
+        mix(&prop.multiProcessorCount, sizeof(prop.multiProcessorCount));
+    }
+    mix(&b->ng, sizeof(b->ng));
+    mix(&b->dtype, sizeof(b->dtype));
+    mix(&b->m, sizeof(b->m));
+    for (const mx_config &c : b->cfg) {
+        mix(c.n, sizeof(c.n));
+        mix(c.d, sizeof(c.d));
+        mix(&c.dt, sizeof(c.dt));
+    }
+    return h;
+}
+
+bool tune_cache_load(mx_batch *b, const std::string &path, uint64_t key)
+{
+    if (path.empty()) return false;
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return false;
+    char line[256];
+    bool hit = false;
+    while (std::fgets(line, sizeof(line), f)) {
+        unsigned long long k = 0;
+        int v[6];
+        if (std::sscanf(line, "%llx %d %d %d %d %d %d", &k, &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) != 7) continue;
+        if (k != key) continue;
+        bool ok = v[0] >= 1 && v[0] <= batch2d::KMAX && v[3] >= 1 && v[3] <= batch2d::KMAX;
+        for (int i : {1, 2, 4, 5}) ok = ok && v[i] >= 8 && v[i] <= 4096;
+        if (!ok) continue;
+        b->spp = v[0]; b->Lf = v[1]; b->Ls = v[2];
+        b->pk = v[3]; b->pLf = v[4]; b->pLs = v[5];
+        hit = true;   // the last matching line wins
+    }
+    std::fclose(f);
+    return hit;
+}
+
+void tune_cache_store(const mx_batch *b, const std::string &path, uint64_t key)
+{
+    if (path.empty()) return;
+    FILE *f = std::fopen(path.c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, "%016llx %d %d %d %d %d %d\n", (unsigned long long)key, b->spp, b->Lf, b->Ls, b->pk, b->pLf,
+                 b->pLs);
+    std::fclose(f);
+}
+
 }  // namespace
 
 extern "C" {
@@ -418,8 +499,13 @@ int mx_batch_init(const mx_config *cfgs, int ngrids, void *stream, void *workspa
     b->Lf = b->Ls = b->pLf = b->pLs = 64;
     b->tuned = false;
     if (cfgs[0].sweeps_per_pass == 0) {
-        rc = b->dtype == MX_F64 ? autotune<double>(b, true, true) : autotune<float>(b, true, true);
-        if (rc) return rc;
+        const std::string path = tune_cache_path();
+        const uint64_t key = tune_key(b);
+        if (!tune_cache_load(b, path, key)) {
+            rc = b->dtype == MX_F64 ? autotune<double>(b, true, true) : autotune<float>(b, true, true);
+            if (rc) return rc;
+            tune_cache_store(b, path, key);
+        }
         b->tuned = true;
     }
     *out = hold.release();

@@ -296,8 +296,12 @@ hipError_t launch_faraday3d(const Coef<T> &c, const T *const E[3], T *const B[3]
 template <typename T>
 hipError_t launch_rhs3d(const Coef<T> &c, const T *const B[3], const T *const Jf[3], T env_src,
                         T *const dEp[3], double *partial, hipStream_t s, int *nwg);
-// one pass of k sweeps (k = 1; k = 2 in FP32, iterate forms FM_STD and
-// FM_DELTA) over a 3D grid, in iterate form `form`
+// one pass of k sweeps over a 3D grid in iterate form `form`, k in
+// [1, stream3d_kmax] (k3s.hip)
+int stream3d_kmax(bool f64);
+template <typename T>
+hipError_t launch_stream3d(const Coef<T> &c, int k, int form, int flags, const SweepArgs<T> &a, hipStream_t s,
+                           int *nwg);
 template <typename T>
 hipError_t launch_sweep3d(const Coef<T> &c, int k, int form, int flags, const SweepArgs<T> &a,
                           hipStream_t s, int *nwg);

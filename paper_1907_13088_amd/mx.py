@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes as C
 import math
 import os
+import sys
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
@@ -351,6 +352,10 @@ class Grid:
             self.h = None
 
     def __del__(self):
+        # at interpreter shutdown the HIP runtime may already be gone: leave
+        # the handle to the process exit instead of calling into it
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -402,6 +407,10 @@ class Batch:
             self.h = None
 
     def __del__(self):
+        # at interpreter shutdown the HIP runtime may already be gone: leave
+        # the handle to the process exit instead of calling into it
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -71,17 +71,24 @@ def _counter(db, name):
     return per
 
 
-def summarize(trace, fetch, write, copy_bytes, bench_json, kernel_re, out, cmds):
-    st = _stats(trace)
+def _calibrate(fetch, write, copy_bytes):
+    """Per-dispatch counters of both runs and the bytes per counter unit,
+    from the largest copy kernel (the probe of copy_bytes)."""
     f = _counter(fetch, "FETCH_SIZE")
     w = _counter(write, "WRITE_SIZE")
     copyk = [k for k in f if "copy" in k.lower() and k in w]
     if not copyk:
         raise SystemExit("no copy kernel in the counter runs (run bench.py with --copy-probe)")
-    ck = max(copyk, key=lambda k: statistics.median(f[k]))
-    fcopy, wcopy = statistics.median(f[ck]), statistics.median(w[ck])
-    # the copy reads and writes copy_bytes: bytes per counter unit
-    ff, fw = copy_bytes / fcopy, copy_bytes / wcopy
+    ck = max(copyk, key=lambda k: max(f[k]))
+    # the probe is the largest copy of the run (the run may hold smaller
+    # copies of the same kernel); it reads and writes copy_bytes
+    fcopy, wcopy = max(f[ck]), max(w[ck])
+    return f, w, ck, fcopy, wcopy, copy_bytes / fcopy, copy_bytes / wcopy
+
+
+def summarize(trace, fetch, write, copy_bytes, bench_json, kernel_re, out, cmds):
+    st = _stats(trace)
+    f, w, ck, fcopy, wcopy, ff, fw = _calibrate(fetch, write, copy_bytes)
     bench = json.loads(open(bench_json).read().strip().splitlines()[-1]) if bench_json else None
     L = []
     L.append("# rocprofv3 summary: 2D field step, 4096 x 4096 TE+TM FP32, m = 20, p = 3 (MI355X, 1 GPU)")
@@ -143,8 +150,10 @@ def summarize(trace, fetch, write, copy_bytes, bench_json, kernel_re, out, cmds)
     return out
 
 
-def trace_summary(trace, title, cmd, out, bench_json=None):
-    """Kernel statistics of one rocprofv3 --kernel-trace --stats run."""
+def trace_summary(trace, title, cmd, out, bench_json=None, fetch=None, write=None, copy_bytes=None,
+                  cmd_fetch=None, cmd_write=None):
+    """Kernel statistics of one rocprofv3 --kernel-trace --stats run, and,
+    given the two counter runs, the HBM traffic per dispatch of every kernel."""
     L = [f"# rocprofv3 summary: {title} (MI355X, 1 GPU)", "", "kernel trace command: `" + cmd + "`", "",
          "| kernel | calls | avg us | total ms | % |", "|---|---:|---:|---:|---:|"]
     for n, c, tot, avg, pct in _stats(trace):
@@ -152,6 +161,19 @@ def trace_summary(trace, title, cmd, out, bench_json=None):
     if bench_json:
         L += ["", "bench.py output of the same command:", "", "```",
               open(bench_json).read().strip().splitlines()[-1], "```"]
+    if fetch and write:
+        f, w, ck, fcopy, wcopy, ff, fw = _calibrate(fetch, write, copy_bytes)
+        L += ["", "HBM traffic per dispatch (one counter per run):", "", "fetch command: `" + cmd_fetch + "`", "",
+              "write command: `" + cmd_write + "`", "",
+              f"calibration: a plain {copy_bytes}-byte device copy ({_short(ck)}) reads FETCH_SIZE = {fcopy:.0f} "
+              f"and WRITE_SIZE = {wcopy:.0f} per dispatch, so one unit is {ff:.1f} B read and {fw:.1f} B written",
+              "", "| kernel | dispatches | read MB | written MB | traffic MB |", "|---|---:|---:|---:|---:|"]
+        for k in sorted(f, key=lambda k: -statistics.mean(f[k])):
+            if k == ck or k not in w:
+                continue
+            rd = statistics.mean(f[k]) * ff
+            wr = statistics.mean(w[k]) * fw
+            L.append(f"| {_short(k)} | {len(f[k])} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | {(rd + wr) / 1e6:.1f} |")
     open(out, "w").write("\n".join(L) + "\n")
     return out
 
@@ -171,7 +193,8 @@ def main():
     ap.add_argument("--cmd-write")
     a = ap.parse_args()
     if a.title:
-        print(trace_summary(a.trace, a.title, a.cmd_trace, a.out, a.bench_json))
+        print(trace_summary(a.trace, a.title, a.cmd_trace, a.out, a.bench_json, a.fetch, a.write, a.copy_bytes,
+                            a.cmd_fetch, a.cmd_write))
         return
     print(summarize(a.trace, a.fetch, a.write, a.copy_bytes, a.bench_json, a.kernel, a.out,
                     (a.cmd_trace, a.cmd_fetch, a.cmd_write)))

@@ -75,10 +75,10 @@ def _cfg(**kw):
     (dict(solver=1, form=1), mx.MX_EINVAL),
     (dict(solver=1, lumped=True), mx.MX_EINVAL),
     (dict(ndim=3, n=(8, 8, 8), d=(1.0, 1.0, 0.5), dt=0.3 / math.sqrt(3), solver=1), mx.MX_EINVAL),
-    (dict(ndim=3, n=(8, 8, 8), dt=0.5 / math.sqrt(3), solver=1, sweeps_per_pass=2), mx.MX_EINVAL),
+    (dict(ndim=3, n=(8, 8, 8), dt=0.5 / math.sqrt(3), solver=1, sweeps_per_pass=4), mx.MX_EINVAL),
     (dict(ndim=3, n=(8, 8, 8), dt=0.5 / math.sqrt(3), blocks=1), mx.MX_EINVAL),
-    (dict(ndim=3, n=(8, 8, 8), dt=0.5 / math.sqrt(3), sweeps_per_pass=3), mx.MX_EINVAL),
-    (dict(ndim=3, n=(8, 8, 8), dt=0.5 / math.sqrt(3), dtype="f64", sweeps_per_pass=2), mx.MX_EINVAL),
+    (dict(ndim=3, n=(8, 8, 8), dt=0.5 / math.sqrt(3), sweeps_per_pass=4), mx.MX_EINVAL),
+    (dict(ndim=3, n=(8, 8, 8), dt=0.5 / math.sqrt(3), dtype="f64", sweeps_per_pass=3), mx.MX_EINVAL),
     (dict(ndim=3, n=(8, 8, 8), dt=0.99 / math.sqrt(2)), mx.MX_ECFL),
 ])
 def test_validation_errors(kw, code):

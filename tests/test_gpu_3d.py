@@ -71,24 +71,48 @@ def test_3d_fp32_delta_tolerance_1e7():
     assert max(e) < 1e-5
 
 
-@pytest.mark.parametrize("shape", [(20, 22, 23), (17, 40, 70), (5, 3, 7)])
-def test_3d_fp32_two_level_pass_equals_single_level_bitwise(shape):
-    """FP32 passes of two sweeps (z-marching, two LDS levels) against passes
-    of one sweep: the same stencil arithmetic in the same order, so the
-    fields agree bitwise; both within 1e-5 of the oracle.  Ragged shapes,
-    some smaller than a workgroup tile."""
+@pytest.mark.parametrize("dtype,solver,shape", [("f32", 0, (20, 22, 23)), ("f32", 0, (17, 40, 70)),
+                                                 ("f32", 0, (5, 3, 7)), ("f64", 0, (20, 22, 23)),
+                                                 ("f64", 1, (19, 35, 41)), ("f32", 1, (20, 22, 23))])
+def test_3d_every_pass_depth_bitwise_and_against_oracle(dtype, solver, shape):
+    """Passes of 1, 2 (and in FP32 3) sweeps marching in z, in Alg 1 and in
+    the Chebyshev form: every level evaluates the same expressions in the
+    same order, so all depths give bitwise equal fields, within 1e-12 (FP64)
+    or 1e-5 (FP32) of the oracle.  Ragged shapes, some smaller than a
+    workgroup tile."""
     w = I.planewave_3d(n=72, kidx=2, npulses=4, sigma=3.0, filter_passes=1, tol=0.0, m_max=9, steps=6,
-                       seed=3010, dtype="f32")
+                       seed=3010, dtype=dtype)
     w = _reshape(w, shape)
-    E2, B2, _, k2 = run_gpu(w, 4, sweeps=9, tol=0.0, spp=2)
-    E1, B1, _, k1 = run_gpu(w, 4, sweeps=9, tol=0.0)
-    assert (k2, k1) == (2, 1)
-    for a, b in zip(E2 + B2, E1 + B1):
-        assert np.array_equal(a, b)
-    Eo, Bo, _ = run_oracle(w, 4, sweeps=9, tol=0.0)
-    e = rel_err(E2 + B2, Eo + Bo)
-    log(f"3D fp32 two-level {shape}: {max(e):.2e}")
-    assert max(e) < 1e-5
+    kmax = 3 if dtype == "f32" else 2
+    runs = {}
+    for k in range(1, kmax + 1):
+        Eg, Bg, _, kk = run_gpu(w, 4, sweeps=9, tol=0.0, spp=k, solver=solver)
+        assert kk == k
+        runs[k] = Eg + Bg
+    for k in range(2, kmax + 1):
+        for a, b in zip(runs[k], runs[1]):
+            assert np.array_equal(a, b), k
+    Eo, Bo, _ = run_oracle(w, 4, sweeps=9, tol=0.0, solver=solver)
+    e = rel_err(runs[kmax], Eo + Bo)
+    log(f"3D {dtype} solver {solver} {shape}, depths 1..{kmax}: {max(e):.2e}")
+    assert max(e) < (1e-12 if dtype == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("spp", [1, 2, 3])
+def test_3d_delta_form_tolerance_every_depth(spp):
+    """The FP32 delta form under tol 1e-7 with its stop test after passes of
+    1, 2 and 3 sweeps: counts within one check of the FP64 oracle testing at
+    the same granularity, and the fields with the oracle's counts replayed
+    within 1e-5 of it."""
+    w = I.planewave_3d(n=32, kidx=1, npulses=4, sigma=3.0, filter_passes=1, tol=1e-7, m_max=300, steps=8,
+                       seed=3006, dtype="f32")
+    Eg, Bg, stg, k = run_gpu(w, 8, form=mx.FORM_DELTA, spp=spp)
+    assert k == spp and all(s.nonconverged[0] == 0 for s in stg)
+    Eo, Bo, sto = run_oracle(w, 8, check_every=spp)
+    for a, b in zip(stg, sto):
+        assert abs(a.sweeps[0] - b.sweeps[0]) <= spp and a.sweeps[0] % spp == 0
+    Eg, Bg, _, _ = run_gpu(w, 8, replay=[s.sweeps for s in sto], form=mx.FORM_DELTA, spp=spp)
+    assert max(rel_err(Eg + Bg, Eo + Bo)) < 1e-5
 
 
 def test_3d_lumped_yee(small3d):
@@ -185,7 +209,7 @@ def test_3d_full_size_sampled_windows_in_bench_configuration():
 
 
 def test_3d_chebyshev_fixed_m_and_tolerance(small3d):
-    """The 3D Chebyshev solve (cubic cells, one sweep per pass): FP64 with a
+    """The 3D Chebyshev solve (cubic cells): FP64 with a
     fixed count within 1e-12 of the oracle's Chebyshev solve on a ragged box;
     under a tolerance the GPU's counts agree with the oracle's (up to a tie),
     need well under half the sweeps of Alg 1, and a replay of the oracle's

@@ -153,3 +153,32 @@ def test_batch_full_workload():
         e = rel_err(to_np(E + B), Eo + Bo)
         log(f"grid {g} {w.shape}: fp32 error after 500 steps {max(e):.2e}")
         assert max(e) < 1e-5
+
+
+def test_tuned_plan_is_cached_on_disk(tmp_path, monkeypatch):
+    """A second init of the same batch reuses the plans the first one timed
+    (read from the cache file instead of timing again): the same schedules,
+    one line in the file, and an init far shorter than the tuning one."""
+    import time
+    import torch
+    path = tmp_path / "plans.txt"
+    monkeypatch.setenv("MX_TUNE_CACHE", str(path))
+    ws = _small_set("f32", seed=801)
+    cfgs = [mx.make_config(2, w.shape[::-1], w.dt, (1.0, 1.0), "f32", mx.MX_ALL, 20, 0.0, 0) for w in ws]
+    t0 = time.perf_counter()
+    b1 = mx.Batch(cfgs)
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t0
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1
+    t0 = time.perf_counter()
+    b2 = mx.Batch(cfgs)
+    torch.cuda.synchronize()
+    t_cached = time.perf_counter() - t0
+    log(f"batch init: tuning {t_tune * 1e3:.1f} ms, from the cache {t_cached * 1e3:.1f} ms")
+    for persistent in (False, True):
+        assert b1.schedule(persistent) == b2.schedule(persistent)
+    assert path.read_text().splitlines() == lines
+    assert t_cached < 0.5 * t_tune
+    b1.close()
+    b2.close()
