@@ -368,21 +368,22 @@ def bench_planewave_te(steps, warm):
                   "note": "latency bound: one cooperative launch runs up to 64 steps, the stop test on the device"})
 
 
-def _run_3d(steps, warm, solver, form):
-    """Step the 512^3 FP32 plane-wave workload (tol 1e-7) with one solver;
+def _run_3d(steps, warm, solver, form, dtype="f32"):
+    """Step the 512^3 plane-wave workload (tol 1e-7) with one solver;
     returns (Gcell-steps/s, details)."""
     import torch
     from paper_1907_13088_amd import inputs as I
     from paper_1907_13088_amd import mx
     t0 = time.time()
-    w = I.planewave_3d(steps=steps + warm)
+    w = I.planewave_3d(steps=steps + warm, dtype=dtype)
     log(f"3D inputs generated in {time.time() - t0:.1f}s")
-    cfg = mx.make_config(3, w.shape[::-1], w.dt, w.d, "f32", 3, w.sweeps, w.tol, w.filter_passes,
+    cfg = mx.make_config(3, w.shape[::-1], w.dt, w.d, dtype, 3, w.sweeps, w.tol, w.filter_passes,
                          form=form, solver=solver, sweeps_per_pass=SPP)
     g = mx.Grid(cfg)
-    E = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in w.E]
-    B = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in w.B]
-    J = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in w.J0]
+    td = torch.float64 if dtype == "f64" else torch.float32
+    E = [torch.tensor(a, dtype=td, device="cuda") for a in w.E]
+    B = [torch.tensor(a, dtype=td, device="cuda") for a in w.B]
+    J = [torch.tensor(a, dtype=td, device="cuda") for a in w.J0]
     del w.E, w.B, w.J0
     g.bind(E, B)
     g.set_current(J)
@@ -411,10 +412,13 @@ def _run_3d(steps, warm, solver, form):
 
 
 def bench_planewave_3d(steps, warm):
-    """512^3, FP32, all six components, tol 1e-7 (delta form)."""
+    """512^3, FP32, all six components, tol 1e-7 (delta form); the same in
+    FP64 beside it (two steps)."""
     from paper_1907_13088_amd import mx
     v, det = _run_3d(steps or 5, 1 if warm is None else warm, mx.SOLVER_ALG1, mx.FORM_DELTA)
-    return _line("512^3 plane wave + 32 pulses, FP32, tol 1e-7", v, "Gcell-steps/s", {**det, "dtype": "f32"})
+    v64, d64 = _run_3d(2, 1, mx.SOLVER_ALG1, mx.FORM_DELTA, "f64")
+    return _line("512^3 plane wave + 32 pulses, FP32, tol 1e-7", v, "Gcell-steps/s",
+                 {**det, "dtype": "f32", "fp64": {**d64, "Gcell_steps_per_s": round(v64, 4)}})
 
 
 def bench_chebyshev_3d(steps, warm):
@@ -429,8 +433,40 @@ def bench_chebyshev_3d(steps, warm):
                   "speedup": round(vc / v1, 3)})
 
 
+def _batch_run(ws, steps, warm, persistent, dtype):
+    """Step the batch with one schedule; returns its result record."""
+    import torch
+    from paper_1907_13088_amd import mx
+    cells = sum(w.cells for w in ws)
+    td = torch.float64 if dtype == "f64" else torch.float32
+    cfgs = [mx.make_config(2, w.shape[::-1], w.dt, (1.0, 1.0), dtype, mx.MX_ALL, w.sweeps, 0.0, 0) for w in ws]
+    b = mx.Batch(cfgs)
+    fields = []
+    for gi, w in enumerate(ws):
+        E = [torch.tensor(a, dtype=td, device="cuda") for a in w.E]
+        B = [torch.tensor(a, dtype=td, device="cuda") for a in w.B]
+        b.bind(gi, E, B)
+        fields.append((E, B))
+    b.step(warm or 2, persistent=persistent)
+    torch.cuda.synchronize()
+    s0, s1 = _events()
+    s0.record()
+    b.step(steps, persistent=persistent)
+    s1.record()
+    torch.cuda.synchronize()
+    ms = s0.elapsed_time(s1)
+    rec = {"Gcell_steps_per_s": round(cells * steps / ms / 1e6, 3), "ms": round(ms, 1),
+           "plan": {**b.schedule(persistent), "persistent_blocks": b.plan()["persistent_blocks"]}}
+    b.close()
+    del fields
+    torch.cuda.empty_cache()
+    return rec
+
+
 def bench_batch(steps, warm):
-    """64 grids of uneven size and Courant number, FP32, m = 20, one persistent launch."""
+    """64 grids of uneven size and Courant number, FP32, m = 20, one persistent
+    launch (and the grouped schedule beside it; both again in FP64 over 100
+    steps)."""
     import torch
     from paper_1907_13088_amd import inputs as I
     from paper_1907_13088_amd import mx
@@ -441,49 +477,36 @@ def bench_batch(steps, warm):
     cells = sum(w.cells for w in ws)
     res = {}
     for persistent in (True, False):
-        cfgs = [mx.make_config(2, w.shape[::-1], w.dt, (1.0, 1.0), "f32", mx.MX_ALL, w.sweeps, 0.0, 0)
-                for w in ws]
-        b = mx.Batch(cfgs)
-        for gi, w in enumerate(ws):
-            b.bind(gi, [torch.tensor(a, dtype=torch.float32, device="cuda") for a in w.E],
-                   [torch.tensor(a, dtype=torch.float32, device="cuda") for a in w.B])
-        b.step(warm or 2, persistent=persistent)
-        torch.cuda.synchronize()
-        s0, s1 = _events()
-        s0.record()
-        b.step(steps, persistent=persistent)
-        s1.record()
-        torch.cuda.synchronize()
-        ms = s0.elapsed_time(s1)
-        res["persistent" if persistent else "grouped"] = {"Gcell_steps_per_s": round(cells * steps / ms / 1e6, 3),
-                                                          "ms": round(ms, 1),
-                                                          "plan": {**b.schedule(persistent),
-                                                                   "persistent_blocks": b.plan()["persistent_blocks"]}}
-        b.close()
+        res["persistent" if persistent else "grouped"] = _batch_run(ws, steps, warm, persistent, "f32")
+    ws64 = I.batch_2d(steps=100, dtype="f64")
+    res["fp64"] = {("persistent" if p else "grouped"): _batch_run(ws64, 100, warm, p, "f64") for p in (True, False)}
     return _line("64 batched 2D grids, FP32, m = 20", res["persistent"]["Gcell_steps_per_s"], "Gcell-steps/s",
                  {"steps": steps, "cells": cells, "dtype": "f32", "schedules": res})
 
 
-def bench_adjoint(steps, warm):
-    """2048^2 FP32, 256 learnable sources, forward + backward with checkpoints every 50 steps."""
+def _adjoint_run(steps, dtype):
+    """Forward and backward of the 2048^2 adjoint workload; returns
+    (forward s, backward s)."""
     import math
     import numpy as np
     import torch
     from paper_1907_13088_amd import inputs as I
     from paper_1907_13088_amd import mx
     from paper_1907_13088_amd.adjoint import SourceSet, field_steps
-    n, nsrc, steps = 2048, 256, steps or 500
-    w = I.modes_2d((n, n), nmodes=64, npulses=0, steps=steps, seed=1005, dtype="f32")
+    n, nsrc = 2048, 256
+    td = torch.float64 if dtype == "f64" else torch.float32
+    npd = np.float64 if dtype == "f64" else np.float32
+    w = I.modes_2d((n, n), nmodes=64, npulses=0, steps=steps, seed=1005, dtype=dtype)
     origins, shapes, amps = I.adjoint_sources_2d(n=n, nsrc=nsrc, seed=1005)
-    shapes = np.asarray(I.round_to(np.float32, shapes))
-    amps = np.asarray(I.round_to(np.float32, amps))
+    shapes = np.asarray(I.round_to(npd, shapes))
+    amps = np.asarray(I.round_to(npd, amps))
     env = [math.sin(0.3 * (s + 0.5) * w.dt) for s in range(steps)]
-    cfg = mx.make_config(2, (n, n), w.dt, (1.0, 1.0), "f32", mx.MX_ALL, 20, 0.0, 3)
+    cfg = mx.make_config(2, (n, n), w.dt, (1.0, 1.0), dtype, mx.MX_ALL, 20, 0.0, 3)
     g = mx.Grid(cfg)
-    src = SourceSet(torch.tensor(origins, device="cuda"), torch.tensor(shapes, dtype=torch.float32, device="cuda"))
+    src = SourceSet(torch.tensor(origins, device="cuda"), torch.tensor(shapes, dtype=td, device="cuda"))
     a = torch.tensor(amps, device="cuda", requires_grad=True)
-    E0 = [torch.tensor(x, dtype=torch.float32, device="cuda", requires_grad=True) for x in w.E]
-    B0 = [torch.tensor(x, dtype=torch.float32, device="cuda", requires_grad=True) for x in w.B]
+    E0 = [torch.tensor(x, dtype=td, device="cuda", requires_grad=True) for x in w.E]
+    B0 = [torch.tensor(x, dtype=td, device="cuda", requires_grad=True) for x in w.B]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     E, B = field_steps(a, E0, B0, g, src, env, steps, checkpoint_every=50, verify=False)
@@ -494,11 +517,25 @@ def bench_adjoint(steps, warm):
     L.backward()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    cells = n * n
-    return _line("2048^2 adjoint, 256 sources, FP32, 500 steps", cells * steps / (t2 - t0) / 1e9, "Gcell-steps/s",
-                 {"steps": steps, "dtype": "f32", "forward_s": round(t1 - t0, 3), "backward_s": round(t2 - t1, 3),
-                  "forward_Gcell_steps_per_s": round(cells * steps / (t1 - t0) / 1e9, 3),
-                  "backward_Gcell_steps_per_s": round(cells * steps / (t2 - t1) / 1e9, 3),
+    g.close()
+    del E, B, E0, B0, a, src
+    torch.cuda.empty_cache()
+    return t1 - t0, t2 - t1
+
+
+def bench_adjoint(steps, warm):
+    """2048^2 FP32, 256 learnable sources, forward + backward with checkpoints
+    every 50 steps (and the same in FP64 beside it)."""
+    steps = steps or 500
+    cells = 2048 * 2048
+    tf, tb = _adjoint_run(steps, "f32")
+    tf64, tb64 = _adjoint_run(steps, "f64")
+    return _line("2048^2 adjoint, 256 sources, FP32, 500 steps", cells * steps / (tf + tb) / 1e9, "Gcell-steps/s",
+                 {"steps": steps, "dtype": "f32", "forward_s": round(tf, 3), "backward_s": round(tb, 3),
+                  "forward_Gcell_steps_per_s": round(cells * steps / tf / 1e9, 3),
+                  "backward_Gcell_steps_per_s": round(cells * steps / tb / 1e9, 3),
+                  "fp64": {"forward_s": round(tf64, 3), "backward_s": round(tb64, 3),
+                           "Gcell_steps_per_s": round(cells * steps / (tf64 + tb64) / 1e9, 3)},
                   "note": "value counts forward and backward (transposed steps and source projection) "
                           "over the same steps; the step is linear, so the backward needs no forward "
                           "state and runs without re-verifying the checkpointed segments"})

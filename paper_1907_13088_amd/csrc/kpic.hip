@@ -39,8 +39,21 @@ __device__ __forceinline__ int wrapn(int i, int n)
     return i < 0 ? i + n : i;
 }
 
-// LDS accumulation tile of the deposition (nodes)
-constexpr int TWX = 32, TWY = 32;
+// the same for indices within a few cells of [0, n): no division
+__device__ __forceinline__ int wrapc(int i, int n)
+{
+    if (i >= 0 && i < n) return i;
+    const int j = i < 0 ? i + n : i - n;
+    return (j >= 0 && j < n) ? j : wrapn(i, n);
+}
+
+// LDS accumulation tile of the deposition (nodes); rows and components
+// padded so that neighbouring nodes of different rows or components fall in
+// different LDS banks
+constexpr int TWX = 32, TWY = 32, TPX = TWX + 1, TPC = TWY * TPX + 3;
+// window contributions of one particle: J_x on 3 x 4 nodes, J_y on 4 x 3,
+// J_z on 4 x 4
+constexpr int NCON = 40;
 
 // min and max of v over the workgroup (valid in every thread)
 __device__ __forceinline__ void block_minmax(int &vmin, int &vmax, int *sh)
@@ -61,45 +74,67 @@ __device__ __forceinline__ void block_minmax(int &vmin, int &vmax, int *sh)
 template <typename T>
 __global__ __launch_bounds__(PT) void k_pic_push(PicArgs<T> a)
 {
-    __shared__ T tile[3][TWY][TWX];
+    __shared__ T tile[3 * TPC];
     __shared__ int sh[2 * PT / 64];
     const int64_t p = (int64_t)blockIdx.x * PT + threadIdx.x;
     const bool live = p < a.np;
     const int nx = a.nx, ny = a.ny;
     const T dx = a.dx, dy = a.dy, dt = a.dt, th = a.th;
-    auto at = [&](const T *F, int i, int j) { return F[(size_t)wrapn(j, ny) * nx + wrapn(i, nx)]; };
     const T x0 = live ? a.x[p] : T(0), y0 = live ? a.y[p] : T(0);
-    // value of a field at the particle: linear shapes around the component's
-    // staggered position (i + ox, j + oy); val(i, j) is the node value
-    auto gather = [&](auto &&val, T ox, T oy) {
-        const T xi = x0 / dx - ox, eta = y0 / dy - oy;
-        const int i0 = (int)floor(xi), j0 = (int)floor(eta);
-        T v = T(0);
-        for (int b = 0; b < 2; b++)
-            for (int c = 0; c < 2; c++) {
-                const T wgt = shape1(xi - T(i0 + c)) * shape1(eta - T(j0 + b));
-                v += wgt * val(i0 + c, j0 + b);
-            }
-        return v;
-    };
     const T *Ex = a.E[0], *Ey = a.E[1], *Ez = a.E[2];
-    const T ex = gather([&](int i, int j) { return at(Ex, i, j); }, T(0.5), T(0));
-    const T ey = gather([&](int i, int j) { return at(Ey, i, j); }, T(0), T(0.5));
-    const T ez = gather([&](int i, int j) { return at(Ez, i, j); }, T(0), T(0));
-    // B^n at the B positions: half a Faraday step (eqs faraday_*, 2D)
-    const T bx = gather([&](int i, int j) {
-        const T dyEz = (at(Ez, i, j + 1) - at(Ez, i, j)) / dy;
-        return at(a.B[0], i, j) - th * (dyEz - T(0));
-    }, T(0), T(0.5));
-    const T by = gather([&](int i, int j) {
-        const T dxEz = (at(Ez, i + 1, j) - at(Ez, i, j)) / dx;
-        return at(a.B[1], i, j) - th * (T(0) - dxEz);
-    }, T(0.5), T(0));
-    const T bz = gather([&](int i, int j) {
-        const T dxEy = (at(Ey, i + 1, j) - at(Ey, i, j)) / dx;
-        const T dyEx = (at(Ex, i, j + 1) - at(Ex, i, j)) / dy;
-        return at(a.B[2], i, j) - th * (dxEy - dyEx);
-    }, T(0.5), T(0.5));
+    T ex, ey, ez, bx, by, bz;
+    {
+        // every stencil below lies in the 4 x 4 nodes from (ic - 1, jc - 1)
+        // around the particle's cell: their wrapped columns and row offsets
+        // are formed once
+        const int ic = (int)floor(x0 / dx), jc = (int)floor(y0 / dy);
+        unsigned cw[4], rw[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            cw[k] = (unsigned)wrapc(ic - 1 + k, nx);
+            rw[k] = (unsigned)wrapc(jc - 1 + k, ny) * (unsigned)nx;
+        }
+        auto pick = [](const unsigned (&w)[4], int k) { return k <= 0 ? w[0] : (k == 1 ? w[1] : (k == 2 ? w[2] : w[3])); };
+        // value of a field at the particle: linear shapes around the
+        // component's staggered position (i + ox, j + oy), the stencil's
+        // nodes i0..i0+1 x j0..j0+1; val(col, row, c, b) reads node
+        // (i0 + c, j0 + b) (columns col[c..c+1], rows row[b..b+1] for the
+        // differences of the half Faraday step)
+        auto gatherw = [&](auto &&val, T ox, T oy) {
+            const T xi = x0 / dx - ox, eta = y0 / dy - oy;
+            const int i0 = (int)floor(xi), j0 = (int)floor(eta);
+            const int si = i0 - ic + 1, sj = j0 - jc + 1;
+            const unsigned col[3] = {pick(cw, si), pick(cw, si + 1), pick(cw, si + 2)};
+            const unsigned row[3] = {pick(rw, sj), pick(rw, sj + 1), pick(rw, sj + 2)};
+            T v = T(0);
+#pragma unroll
+            for (int b = 0; b < 2; b++)
+#pragma unroll
+                for (int c = 0; c < 2; c++) {
+                    const T wgt = shape1(xi - T(i0 + c)) * shape1(eta - T(j0 + b));
+                    v += wgt * val(col, row, c, b);
+                }
+            return v;
+        };
+        using U3 = const unsigned (&)[3];
+        ex = gatherw([&](U3 cl, U3 rw_, int c, int b) { return Ex[rw_[b] + cl[c]]; }, T(0.5), T(0));
+        ey = gatherw([&](U3 cl, U3 rw_, int c, int b) { return Ey[rw_[b] + cl[c]]; }, T(0), T(0.5));
+        ez = gatherw([&](U3 cl, U3 rw_, int c, int b) { return Ez[rw_[b] + cl[c]]; }, T(0), T(0));
+        // B^n at the B positions: half a Faraday step (eqs faraday_*, 2D)
+        bx = gatherw([&](U3 cl, U3 rw_, int c, int b) {
+            const T dyEz = (Ez[rw_[b + 1] + cl[c]] - Ez[rw_[b] + cl[c]]) / dy;
+            return a.B[0][rw_[b] + cl[c]] - th * (dyEz - T(0));
+        }, T(0), T(0.5));
+        by = gatherw([&](U3 cl, U3 rw_, int c, int b) {
+            const T dxEz = (Ez[rw_[b] + cl[c + 1]] - Ez[rw_[b] + cl[c]]) / dx;
+            return a.B[1][rw_[b] + cl[c]] - th * (T(0) - dxEz);
+        }, T(0.5), T(0));
+        bz = gatherw([&](U3 cl, U3 rw_, int c, int b) {
+            const T dxEy = (Ey[rw_[b] + cl[c + 1]] - Ey[rw_[b] + cl[c]]) / dx;
+            const T dyEx = (Ex[rw_[b + 1] + cl[c]] - Ex[rw_[b] + cl[c]]) / dy;
+            return a.B[2][rw_[b] + cl[c]] - th * (dxEy - dyEx);
+        }, T(0.5), T(0.5));
+    }
     // Boris: half electric kick, rotation about B, half electric kick
     const T h = a.h;
     const T umx = (live ? a.ux[p] : T(0)) + h * ex, umy = (live ? a.uy[p] : T(0)) + h * ey,
@@ -139,37 +174,60 @@ __global__ __launch_bounds__(PT) void k_pic_push(PicArgs<T> a)
     const int bw = imax + 4 - imin, bh = jmax + 4 - jmin;
     const bool in_lds = imax >= imin && bw <= TWX && bh <= TWY;
     if (in_lds) {
-        for (int e = threadIdx.x; e < 3 * bw * bh; e += PT) {
-            const int c = e / (bw * bh), r = e % (bw * bh);
-            tile[c][r / bw][r % bw] = T(0);
-        }
+        for (int e = threadIdx.x; e < 3 * TPC; e += PT) tile[e] = T(0);
         __syncthreads();
     }
-    auto add = [&](int comp, int k, int l, T v) {
-        if (v == T(0)) return;
-        if (in_lds) atomicAdd(&tile[comp][j0 + l - jmin][i0 + k - imin], v);
-        else unsafeAtomicAdd(&a.J[comp][(size_t)wrapn(j0 + l, ny) * nx + wrapn(i0 + k, nx)], v);
+    // contribution e of the window: J_x at (k, l) = (e % 3, e / 3) for
+    // e < 12, J_y at (k, l) = ((e - 12) / 3, (e - 12) % 3) for e < 24, J_z at
+    // (k, l) = ((e - 24) % 4, (e - 24) / 4)
+    auto node = [](int e, int &comp, int &k, int &l) {
+        if (e < 12) { comp = 0; k = e % 3; l = e / 3; }
+        else if (e < 24) { comp = 1; k = (e - 12) / 3; l = (e - 12) % 3; }
+        else { comp = 2; k = (e - 24) % 4; l = (e - 24) / 4; }
     };
-    if (live) {
-        for (int l = 0; l < 4; l++) {
-            T run = T(0);   // sum of W_x over the window's nodes up to k
-            for (int k = 0; k < 3; k++) {
-                run += T(0.5) * (sx1[k] - sx0[k]) * (sy0[l] + sy1[l]);
-                add(0, k, l, a.cx * run);
-            }
+    T con[NCON];
+#pragma unroll
+    for (int l = 0; l < 4; l++) {
+        T run = T(0);   // sum of W_x over the window's nodes up to k
+        for (int k = 0; k < 3; k++) {
+            run += T(0.5) * (sx1[k] - sx0[k]) * (sy0[l] + sy1[l]);
+            con[3 * l + k] = a.cx * run;
         }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        T run = T(0);   // sum of W_y over the window's nodes up to l
+        for (int l = 0; l < 3; l++) {
+            run += T(0.5) * (sy1[l] - sy0[l]) * (sx0[k] + sx1[k]);
+            con[12 + 3 * k + l] = a.cy * run;
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < 4; l++)
+#pragma unroll
         for (int k = 0; k < 4; k++) {
-            T run = T(0);   // sum of W_y over the window's nodes up to l
-            for (int l = 0; l < 3; l++) {
-                run += T(0.5) * (sy1[l] - sy0[l]) * (sx0[k] + sx1[k]);
-                add(1, k, l, a.cy * run);
-            }
+            const T wz = (T(2) * sx0[k] * sy0[l] + sx1[k] * sy0[l] + sx0[k] * sy1[l] + T(2) * sx1[k] * sy1[l]) / T(6);
+            con[24 + 4 * l + k] = a.cz * vz * wz;
         }
-        for (int l = 0; l < 4; l++)
-            for (int k = 0; k < 4; k++) {
-                const T wz = (T(2) * sx0[k] * sy0[l] + sx1[k] * sy0[l] + sx0[k] * sy1[l] + T(2) * sx1[k] * sy1[l]) / T(6);
-                add(2, k, l, a.cz * vz * wz);
+    if (in_lds) {
+        if (live)
+#pragma unroll
+            for (int e = 0; e < NCON; e++) {
+                if (con[e] == T(0)) continue;
+                int comp, k, l;
+                node(e, comp, k, l);
+                atomicAdd(&tile[comp * TPC + (j0 + l - jmin) * TPX + (i0 + k - imin)], con[e]);
             }
+    } else if (live) {
+#pragma unroll
+        for (int e = 0; e < NCON; e++) {
+            if (con[e] == T(0)) continue;
+            int comp, k, l;
+            node(e, comp, k, l);
+            unsafeAtomicAdd(&a.J[comp][(size_t)wrapc(j0 + l, ny) * nx + wrapc(i0 + k, nx)], con[e]);
+        }
+    }
+    if (live) {
         a.x[p] = x1 >= a.Lx ? x1 - a.Lx : (x1 < T(0) ? x1 + a.Lx : x1);
         a.y[p] = y1 >= a.Ly ? y1 - a.Ly : (y1 < T(0) ? y1 + a.Ly : y1);
         a.ux[p] = nux;
@@ -180,9 +238,9 @@ __global__ __launch_bounds__(PT) void k_pic_push(PicArgs<T> a)
         __syncthreads();
         for (int e = threadIdx.x; e < 3 * bw * bh; e += PT) {
             const int c = e / (bw * bh), r = e % (bw * bh);
-            const T v = tile[c][r / bw][r % bw];
+            const T v = tile[c * TPC + (r / bw) * TPX + r % bw];
             if (v != T(0))
-                unsafeAtomicAdd(&a.J[c][(size_t)wrapn(jmin + r / bw, ny) * nx + wrapn(imin + r % bw, nx)], v);
+                unsafeAtomicAdd(&a.J[c][(size_t)wrapc(jmin + r / bw, ny) * nx + wrapc(imin + r % bw, nx)], v);
         }
     }
 }
