@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # build): 256 CUs x 64 lanes x 2 flops x 2.4 GHz
 VALU_FP32_PEAK_TFLOPS = 78.6
 HERE = os.path.dirname(os.path.abspath(__file__))
-PROFILE_SUMMARY = os.path.join(HERE, "profiles", "sweep_pass_2d_4096sq_f32.md")
+PROFILE_SUMMARY = os.path.join(HERE, "profiles", "step_2d_4096sq_f32.md")
 # per-launch timing events are recorded on the last steps of the timed
 # region: all of it below PSTRIDE steps, else an even count near K / 4 (the
 # event records cost about 3 us per launch; even step counts per call let
@@ -60,7 +60,7 @@ def main():
     ap.add_argument("--spp", type=int, default=0, help="sweeps per pass (0 = library choice)")
     ap.add_argument("--variant", type=int, default=0,
                     help="2D sweep kernel: 0 library choice, 1 LDS tile, 2 row streaming, "
-                         "3 row streaming per block")
+                         "3 row streaming per block, 4 row streaming with the front fused into the first pass")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="minimum CPU time of the oracle sample (whole steps, at most 8)")
     ap.add_argument("--no-fp64", action="store_true")
@@ -222,11 +222,6 @@ def main():
                              "GBps": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None,
                              "share": round(v["ms"] / total_ms, 4)}
     log(f"kernels: {json.dumps(kernels)}")
-    sw = prof["sweep"]
-    nl = max(sw["launches"], 1)
-    avg_s = sw["ms"] / 1e3 / nl
-    bytes_per_launch = sw["bytes"] / nl
-    achieved = bytes_per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
     k = g32.block_sweeps_per_pass[0]
     # pass depths of a fixed count: the fewest passes, deeper ones last
     depths, rem = [], w.sweeps
@@ -234,21 +229,42 @@ def main():
         kk = rem // -(-rem // k)
         depths.append(kk)
         rem -= kk
-    store = depths[:-1]
-    traffic = profsum.traffic_per_launch(PROFILE_SUMMARY)
-    # FP32 flops of one sweep of the implemented stencils (an FMA counts 2):
-    # TE 18 per cell (Ex 9, Ey 9), TM 15 per cell
-    flops_per_launch = 33.0 * ncell * sum(store) / max(len(store), 1)
+    fused = prof["front_sweep"]["launches"] > 0
+    store = depths[1:-1] if fused else depths[:-1]
+    # FP32 flops per cell of the implemented stencils (an FMA counts 2): a
+    # sweep 33 (TE 18, TM 15); the front about 120 (Faraday 12, the 7-tap x
+    # filter 42 and 3 cascaded y passes 36 of the current, dE' 30)
+    FRONT_FLOPS, SWEEP_FLOPS = 120.0, 33.0
+    desc = {
+        "front_sweep": (f"k2_front_sweep<float,P=3,K={depths[0]}>: Faraday, current filter and dE' fused with the "
+                        f"first {depths[0]} sweeps (stores B, dE' and the iterate)",
+                        FRONT_FLOPS + SWEEP_FLOPS * depths[0],
+                        "row streaming with one LDS exchange and barrier per row step, two waves per SIMD "
+                        "(254 VGPRs): the sweep levels' latency chain overlaps the front's HBM streams"),
+        "sweep": (f"k2_stream<float,3,K> row-streaming sweep passes storing their iterate "
+                  f"(K = {'+'.join(map(str, store))})",
+                  SWEEP_FLOPS * sum(store) / max(len(store), 1),
+                  "the 6- and 7-sweep passes are bound neither by HBM nor by VALU: each row step waits on an "
+                  "LDS neighbour exchange and barrier (measured against memory-only twins of the passes)"),
+        "sweep_last": (f"k2_stream<float,3,{depths[-1]}> final pass adding the result into E",
+                       SWEEP_FLOPS * depths[-1], "as the other sweep passes; reads three arrays more"),
+        "front": ("k2_front_stream<float,3,P=3>: Faraday, current filter and dE'", FRONT_FLOPS,
+                  "HBM streams with halo rows of the chunked strips"),
+    }
+    dom = max((c for c in desc if prof[c]["launches"] > 0), key=lambda c: prof[c]["ms"])
+    dv = prof[dom]
+    nl = max(dv["launches"], 1)
+    avg_s = dv["ms"] / 1e3 / nl
+    bytes_per_launch = dv["bytes"] / nl
+    achieved = bytes_per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
+    traffic = profsum.traffic_per_launch(PROFILE_SUMMARY, dom)
+    flops_per_launch = desc[dom][1] * ncell
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": f"k2_stream<float,3,K> row-streaming sweep passes storing their iterate "
-                          f"(K = {'+'.join(map(str, store))}; final pass K = {depths[-1]} adds into E)",
+                "kernel": desc[dom][0], "category": dom,
                 "bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_s * 1e6, 2), "launches": nl,
                 "timed_launches": f"HIP events on every launch of the last {nprof} of the {K} timed steps",
-                "limiter": "the 6- and 7-sweep passes are bound neither by HBM nor by VALU: each row step "
-                           "waits on an LDS neighbour exchange and barrier (measured against memory-only "
-                           "twins of the passes); shallower passes reach 56% of the HBM peak but take "
-                           "more passes per step",
+                "limiter": desc[dom][2],
                 "valu_tflops": round(flops_per_launch / avg_s / 1e12, 2) if avg_s > 0 else None,
                 "valu_peak_tflops": VALU_FP32_PEAK_TFLOPS,
                 "step_hbm_GBps": round(sum(v["bytes"] for v in prof.values()) / (total_ms / 1e3) / 1e9, 1),

@@ -111,7 +111,7 @@ typedef struct mx_config {
                              delta 9, 4; TM 16 (FP32), 8 (FP64).  LDS tile: <= 8.
                              3D: up to 3 in FP32, 2 in FP64 (library choice: the
                              most allowed). */
-    int variant;          /* 2D sweep kernel: 0 library choice (FP32: 2, FP64 and
+    int variant;          /* 2D sweep kernel: 0 library choice (FP32: 4, FP64 and
                              the Chebyshev solve: 3; Alg 1 on a grid whose
                              streaming pass would have fewer workgroups than
                              half the CUs: 1),
@@ -119,7 +119,11 @@ typedef struct mx_config {
                              sweeps deep in FP32, 4 in FP64, 8 under a
                              tolerance), 2 row streaming
                              (both blocks per pass), 3 row streaming (each block
-                             on its own) */
+                             on its own), 4 as 2 with the front (Faraday,
+                             filter, dE') run in the same pass as the first
+                             sweeps (FP32, fixed m of Alg 1 in more than one
+                             pass, m / ceil(m / spp) in 3..6, p <= 4; other
+                             steps run as in 2) */
     int solver;           /* MX_SOLVER_ALG1 (default) or MX_SOLVER_CHEBYSHEV (2D,
                              and 3D with cubic cells); the
                              2D Chebyshev passes fuse at most: both blocks 5
@@ -242,7 +246,8 @@ int mx_step_static(const mx_config *cfg, void *stream, void *const E[3], void *c
 #define MX_PROF_ADJOINT    3  /* transposed curls and the filter of the adjoint */
 #define MX_PROF_SWEEP_LAST 4  /* final sweep passes with E += result fused */
 #define MX_PROF_PARTICLES  5  /* particle push and deposition (bytes: the phase space read and written) */
-#define MX_PROF_NCAT       6
+#define MX_PROF_FRONT_SWEEP 6 /* the front fused with the first sweep pass (2D variant 4) */
+#define MX_PROF_NCAT       7
 typedef struct mx_profile {
     int64_t launches[MX_PROF_NCAT];
     double ms[MX_PROF_NCAT];     /* summed kernel time per category */

@@ -80,7 +80,7 @@ void pass_depths(const mx_config *c, int variant, int out[2])
     const bool tolmode = c->tol > 0.0;
     const bool delta = tolmode && c->form == MX_FORM_DELTA;
     const int form = c->solver == MX_SOLVER_CHEBYSHEV ? mx::FM_CHEB : delta ? mx::FM_DELTA : mx::FM_STD;
-    const bool joint = variant == 2 && c->blocks == MX_ALL;
+    const bool joint = (variant == 2 || variant == 4) && c->blocks == MX_ALL;
     const int kmax[2] = {mx::stream2d_kmax(f64, joint ? 3 : 1, form), mx::stream2d_kmax(f64, joint ? 3 : 2, form)};
     for (int b = 0; b < 2; b++) {
         int k = c->sweeps_per_pass > 0 ? c->sweeps_per_pass : kmax[b];
@@ -161,7 +161,8 @@ struct mx_grid {
     int spec[2] = {1, 1}; // passes per block the last tolerance solve ran (queued ahead next step)
     int spp[2];           // sweeps per pass of the TE and TM blocks (3D: [0])
     int variant;          // 2D sweep kernel in use: 1 LDS tile, 2 row streaming (blocks
-                          // together), 3 row streaming (each block on its own)
+                          // together), 3 row streaming (each block on its own), 4 as 2
+                          // with the front fused into the first pass where possible
     Coef<float> cf;
     Coef<double> cd;
     // Chebyshev solve: per block, the factors (previous increment, residual)
@@ -296,16 +297,18 @@ static void grid_setup(mx_grid *g, const mx_config *cfg, hipStream_t stream, int
     g->bound = false;
     g->has_j = false;
     g->hred = nullptr;
-    // library choice: FP32 runs both blocks in one pass (7 sweeps deep);
-    // FP64, whose joint passes are only 3 deep, runs each block on its own
-    // (TE 5, TM 8 deep), which moves fewer bytes per step; so does the
-    // Chebyshev solve (joint passes 5 deep in FP32, per block 8 and 12:
-    // measured 0.46 against 0.60 ms per 4096^2 step at 7 sweeps).  A grid
-    // too small for the row-streaming passes to occupy half the CUs runs
-    // the LDS-tile kernel instead (128^2 to 768^2: 1.4 to 2.8 times faster
-    // per step; the Chebyshev solve has no tile form)
+    // library choice: FP32 runs both blocks in one pass (7 sweeps deep),
+    // the front fused with the first pass where a kernel exists for it
+    // (4096^2, m = 20, p = 3: 0.648 against 0.702 ms per step); FP64, whose
+    // joint passes are only 3 deep, runs each block on its own (TE 5, TM 8
+    // deep), which moves fewer bytes per step; so does the Chebyshev solve
+    // (joint passes 5 deep in FP32, per block 8 and 12: measured 0.46
+    // against 0.60 ms per 4096^2 step at 7 sweeps).  A grid too small for
+    // the row-streaming passes to occupy half the CUs runs the LDS-tile
+    // kernel instead (128^2 to 768^2: 1.4 to 2.8 times faster per step; the
+    // Chebyshev solve has no tile form)
     g->variant = cfg->variant > 0 ? cfg->variant
-                                  : (cfg->dtype == MX_F64 || cfg->solver == MX_SOLVER_CHEBYSHEV ? 3 : 2);
+                                  : (cfg->dtype == MX_F64 || cfg->solver == MX_SOLVER_CHEBYSHEV ? 3 : 4);
     if (cfg->variant == 0 && cfg->ndim == 2 && cfg->solver != MX_SOLVER_CHEBYSHEV) {
         int cu = 0;
         if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cu < 1)
@@ -406,7 +409,7 @@ int mx_validate(const mx_config *c, int *warn)
         if (c->lumped) return fail(MX_EINVAL, "the lumped scheme has A = 0: no solve to accelerate");
     }
     if (c->sweeps_per_pass < 0 || c->sweeps_per_pass > 16) return fail(MX_EINVAL, "sweeps_per_pass must be in [0, 16]");
-    if (c->variant < 0 || c->variant > 3) return fail(MX_EINVAL, "variant must be 0, 1, 2 or 3");
+    if (c->variant < 0 || c->variant > 4) return fail(MX_EINVAL, "variant must be 0, 1, 2, 3 or 4");
     if (c->variant == 1 && c->sweeps_per_pass > 8)
         return fail(MX_EINVAL, "the LDS-tile kernel runs at most 8 sweeps per pass");
     if (c->ndim == 3 && c->sweeps_per_pass > mx::stream3d_kmax(c->dtype == MX_F64))
@@ -750,9 +753,16 @@ int solve_tol(mx_grid *g, void *const rhs[3], const int *target_in, const T **re
 // cut into the fewest passes of at most spp sweeps, of nearly equal depth
 // (deeper ones last: the final pass also reads and writes E, so its sweeps
 // are the cheapest).
+// The front of a step when it runs fused with the first sweep pass
+template <typename T>
+struct FusedFront {
+    FrontArgs<T> a;
+    const T *Bin[3];
+};
+
 template <typename T>
 int run_sweeps(mx_grid *g, void *const rhs[3], const int *target_in, bool tolmode, void *E_fuse[3],
-               bool e_done[2], const T **res, mx_step_stats *st)
+               bool e_done[2], const T **res, mx_step_stats *st, const FusedFront<T> *ff = nullptr)
 {
     e_done[0] = e_done[1] = false;
     if (tolmode) return solve_tol<T>(g, rhs, target_in, res, st);
@@ -801,7 +811,12 @@ int run_sweeps(mx_grid *g, void *const rhs[3], const int *target_in, bool tolmod
                 for (int b = 0; b < 2; b++) pass_cheb<T>(g, b, done[b], kk, a);
             int nwg = 0;
             hipError_t e;
-            {
+            if (ff && first) {
+                // the front and this pass in one (the caller checked that the
+                // pass is the first of both blocks and not the last)
+                ProfScope ps(g, MX_PROF_FRONT_SWEEP, (double)g->ncell * sizeof(T) * (g->has_j ? 18 : 15));
+                e = launch_front_sweep2d<T>(k, c.filter_passes, kk, ff->a, ff->Bin, a, g->stream, &nwg);
+            } else {
                 const int ncomp = c.ndim == 3 ? 3 : ((act & 1) ? 2 : 0) + ((act & 2) ? 1 : 0);
                 ProfScope ps(g, fin ? MX_PROF_SWEEP_LAST : MX_PROF_SWEEP,
                              (double)g->ncell * sizeof(T) * pass_arrays(cheb, false, first, fin) * ncomp);
@@ -935,6 +950,22 @@ int step_impl(mx_grid *g, int nsteps, const double *env, const int *replay, mx_s
         const double e = env ? env[s] : 0.0;
         const T env_src = (T)(e * c.four_pi * c.dt);
         int nwg = 0;
+        int target[2];
+        for (int b = 0; b < 2; b++) {
+            target[b] = replay ? replay[2 * s + b] : c.sweeps;
+            if (!replay && c.lumped) target[b] = 0;
+            if (target[b] < 0) return fail(MX_EINVAL, "negative replayed sweep count at step %d", s);
+        }
+        // the front runs fused with the first sweep pass when both blocks
+        // take the same count of Alg 1 sweeps in more than one pass and that
+        // first pass's depth has a fused kernel
+        FusedFront<T> ff{};
+        bool fuse = false;
+        if (c.ndim == 2 && g->variant == 4 && !tolmode && c.solver == MX_SOLVER_ALG1 && !c.lumped &&
+            c.blocks == MX_ALL && target[0] == target[1] && target[0] > g->spp[0]) {
+            const int m = target[0], kk = m / ((m + g->spp[0] - 1) / g->spp[0]);
+            fuse = front_sweep2d_ok(c.dtype == MX_F64, kk, g->has_j ? c.filter_passes : 0);
+        }
         if (c.ndim == 2) {
             const T *Bin[3];
             T *Bout[3];
@@ -951,10 +982,14 @@ int step_impl(mx_grid *g, int nsteps, const double *env, const int *replay, mx_s
             }
             a.env_src = env_src;
             a.partial = tolmode ? g->partial : nullptr;
+            if (fuse) {
+                ff.a = a;
+                for (int q = 0; q < 3; q++) ff.Bin[q] = Bin[q];
+            }
             const double fb = (double)g->ncell * sizeof(T) *
                               (((c.blocks & 1) ? (g->has_j ? 8 : 6) : 0) + ((c.blocks & 2) ? (g->has_j ? 7 : 6) : 0));
-            hipError_t er;
-            {
+            hipError_t er = hipSuccess;
+            if (!fuse) {
                 ProfScope ps(g, MX_PROF_FRONT, fb);
                 er = launch_front_stream2d<T>(k, c.blocks, c.filter_passes, a, Bin, g->stream, &nwg);
             }
@@ -1013,16 +1048,11 @@ int step_impl(mx_grid *g, int nsteps, const double *env, const int *replay, mx_s
             HIPCHK(launch_reduce2(g->partial, nwg, g->red, g->stream));
             HIPCHK(launch_tol_init(g->tol, g->red, nblk, g->stream));
         }
-        int target[2];
-        for (int b = 0; b < 2; b++) {
-            target[b] = replay ? replay[2 * s + b] : c.sweeps;
-            if (!replay && c.lumped) target[b] = 0;
-            if (target[b] < 0) return fail(MX_EINVAL, "negative replayed sweep count at step %d", s);
-        }
         const T *res[3];
         bool e_done[2] = {false, false};
         mx_step_stats st{};
-        int rc = run_sweeps<T>(g, g->dEp, target, tolmode, g->E, e_done, res, stats ? &st : nullptr);
+        int rc = run_sweeps<T>(g, g->dEp, target, tolmode, g->E, e_done, res, stats ? &st : nullptr,
+                               fuse ? &ff : nullptr);
         if (rc) return rc;
         {
             // E += dE per block not fused into its last pass (the components

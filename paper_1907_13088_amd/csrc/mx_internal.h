@@ -209,6 +209,13 @@ template <typename T>
 hipError_t launch_stream2d(const Coef<T> &c, int block, int k, int form, int flags, const SweepArgs<T> &a,
                            hipStream_t s, int *nwg, int slots);
 int stream2d_kmax(bool f64, int block, int form);
+// the front and the first pass of k sweeps of both blocks (standard form,
+// storing the iterate) in one row-streaming pass (k2fs.hip); available for
+// the (dtype, k, filter passes) where front_sweep2d_ok holds
+bool front_sweep2d_ok(bool f64, int k, int filter_passes);
+template <typename T>
+hipError_t launch_front_sweep2d(const Coef<T> &c, int filter_passes, int k, const FrontArgs<T> &fa,
+                                const T *const Bin[3], const SweepArgs<T> &sa, hipStream_t s, int *nwg);
 template <typename T>
 hipError_t launch_update(int64_t n, int comp_mask, T *const E[3], const T *const X[3], hipStream_t s);
 

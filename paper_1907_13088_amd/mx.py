@@ -21,7 +21,7 @@ MX_OK, MX_EINVAL, MX_ECFL, MX_EWORKSPACE, MX_EDEVICE, MX_ENONFINITE, MX_ESTATE =
 MX_F32, MX_F64 = 0, 1
 MX_TE, MX_TM, MX_ALL = 1, 2, 3
 FORM_STANDARD, FORM_DELTA = 0, 1
-VARIANT_AUTO, VARIANT_TILE, VARIANT_STREAM, VARIANT_STREAM_BLOCK = 0, 1, 2, 3
+VARIANT_AUTO, VARIANT_TILE, VARIANT_STREAM, VARIANT_STREAM_BLOCK, VARIANT_STREAM_FUSED = 0, 1, 2, 3, 4
 SOLVER_ALG1, SOLVER_CHEBYSHEV = 0, 1
 WARN_NOCONV_GUARANTEE = 1
 
@@ -49,10 +49,10 @@ class CConfig(C.Structure):
 
 
 class CProfile(C.Structure):
-    _fields_ = [("launches", C.c_int64 * 6), ("ms", C.c_double * 6), ("bytes", C.c_double * 6)]
+    _fields_ = [("launches", C.c_int64 * 7), ("ms", C.c_double * 7), ("bytes", C.c_double * 7)]
 
 
-PROF_CATEGORIES = ("front", "sweep", "other", "adjoint", "sweep_last", "particles")
+PROF_CATEGORIES = ("front", "sweep", "other", "adjoint", "sweep_last", "particles", "front_sweep")
 
 
 class CStats(C.Structure):

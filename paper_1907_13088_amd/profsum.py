@@ -28,7 +28,8 @@ import statistics
 HERE = os.path.dirname(os.path.abspath(__file__))
 # sources that determine the 2D sweep pass kernels and their launch shapes
 SWEEP_SOURCES = ("csrc/k2s_impl.h", "csrc/stencil2d.h", "csrc/mx_internal.h", "csrc/k2s.hip",
-                 "csrc/k2s_f32_all.hip", "csrc/mx_api.cpp")
+                 "csrc/k2s_f32_all.hip", "csrc/k2f_impl.h", "csrc/k2f.hip", "csrc/k2fs_impl.h", "csrc/k2fs.hip",
+                 "csrc/mx_api.cpp")
 
 
 def source_sha(files=SWEEP_SOURCES) -> str:
@@ -39,15 +40,19 @@ def source_sha(files=SWEEP_SOURCES) -> str:
     return h.hexdigest()
 
 
-def traffic_per_launch(path: str):
+def traffic_per_launch(path: str, category: str = None):
     """Measured HBM bytes per launch of the summarised kernel, or None when
-    the summary is missing or was taken on other kernel sources."""
+    the summary is missing, covers another kernel category or was taken on
+    other kernel sources."""
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m1 = re.search(r"^traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt, re.M)
     m2 = re.search(r"^source_sha256:\s*([0-9a-f]+)", txt, re.M)
+    m3 = re.search(r"^category:\s*(\S+)", txt, re.M)
     if not m1 or not m2 or m2.group(1) != source_sha():
+        return None
+    if category is not None and (not m3 or m3.group(1) != category):
         return None
     return float(m1.group(1))
 
@@ -137,14 +142,16 @@ def summarize(trace, fetch, write, copy_bytes, bench_json, kernel_re, out, cmds)
     L.append("")
     if not sel_calls or not sel_rd:
         raise SystemExit(f"kernel /{kernel_re}/ not found in the runs")
-    L.append(f"dominant kernel: {', '.join('`' + n + '`' for n in sel_names)} (one category: the sweep passes "
-             f"that store their iterate), {sel_calls} calls, rocprofv3 average {sel_total / sel_calls:.1f} us")
+    cat = bench["roofline"].get("category", "sweep") if bench else "sweep"
+    L.append(f"dominant kernel: {', '.join('`' + n + '`' for n in sel_names)} (library category {cat}), "
+             f"{sel_calls} calls, rocprofv3 average {sel_total / sel_calls:.1f} us")
     if bench:
         r = bench["roofline"]
         L.append(f"bench.py HIP-event average of the same launches: {r['avg_launch_us']} us, "
                  f"algorithmic {r['bytes_per_launch'] / 1e6:.1f} MB per launch ({r['achieved']} GB/s)")
     L.append("")
     L.append(f"traffic_bytes_per_launch: {statistics.mean(sel_rd) + statistics.mean(sel_wr):.0f}")
+    L.append(f"category: {cat}")
     L.append(f"source_sha256: {source_sha()}")
     open(out, "w").write("\n".join(L) + "\n")
     return out

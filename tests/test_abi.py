@@ -69,6 +69,7 @@ def _cfg(**kw):
     (dict(filter_passes=9), mx.MX_EINVAL),
     (dict(sweeps_per_pass=17), mx.MX_EINVAL),
     (dict(sweeps_per_pass=9, variant=1), mx.MX_EINVAL),
+    (dict(variant=5), mx.MX_EINVAL),
     (dict(form=7), mx.MX_EINVAL),
     (dict(solver=2), mx.MX_EINVAL),
     (dict(solver=1, variant=1), mx.MX_EINVAL),

@@ -98,7 +98,7 @@ def test_pass_depth_and_kernel_invariance_is_bitwise(small_modes):
     where iterates live, not the arithmetic: FP32 results are bitwise equal."""
     w = small_modes
     ref_out = None
-    for variant in VARIANTS:
+    for variant in VARIANTS + [mx.VARIANT_STREAM_FUSED]:
         for spp in (1, 3, 5, 8) + ((0, 9, 12, 16) if variant == mx.VARIANT_STREAM_BLOCK else (0,)):
             Eg, Bg, _, _ = run_gpu(w, 6, dtype="f32", spp=spp, variant=variant)
             if ref_out is None:
