@@ -11,7 +11,7 @@ None so that no stale traffic is reported.
 
     python -m paper_1907_13088_amd.profsum --trace T.db --fetch F.db --write W.db \\
         --copy-bytes N --bench-json bench.json --kernel REGEX --out profiles/NAME.md \\
-        --cmd-trace "..." --cmd-fetch "..." --cmd-write "..."
+        --cmd-trace "..." --cmd-fetch "..." --cmd-write "..." [--sq S.db --cmd-sq "..."]
     python -m paper_1907_13088_amd.profsum --trace T.db --title TITLE --cmd-trace "..." \\
         [--bench-json bench.json] --out profiles/NAME.md
 """
@@ -91,7 +91,26 @@ def _calibrate(fetch, write, copy_bytes):
     return f, w, ck, fcopy, wcopy, copy_bytes / fcopy, copy_bytes / wcopy
 
 
-def summarize(trace, fetch, write, copy_bytes, bench_json, kernel_re, out, cmds):
+def _sq_table(db, cmd):
+    """Per-kernel means of the SQ counters of one counter run (instruction
+    counts are per dispatch, summed over the wavefronts)."""
+    cur = sqlite3.connect(db).cursor()
+    per = {}
+    for k, n, v in cur.execute("select kernel_name, counter_name, value from counters_collection"):
+        per.setdefault(k, {}).setdefault(n, []).append(float(v))
+    names = sorted({n for d in per.values() for n in d})
+    L = ["SQ counters per dispatch (means; instruction counts summed over wavefronts):", "",
+         "command: `" + cmd + "`", "",
+         "| kernel | " + " | ".join(names) + " |", "|---|" + "---:|" * len(names)]
+    for k in sorted(per, key=lambda k: -statistics.mean(per[k].get("SQ_WAVES", [0.0]))):
+        if "copy" in k.lower() or "elementwise" in k.lower():
+            continue
+        L.append(f"| {_short(k)} | " + " | ".join(f"{statistics.mean(per[k][n]):.4g}" if n in per[k] else "-"
+                                                 for n in names) + " |")
+    return L + [""]
+
+
+def summarize(trace, fetch, write, copy_bytes, bench_json, kernel_re, out, cmds, sq=None):
     st = _stats(trace)
     f, w, ck, fcopy, wcopy, ff, fw = _calibrate(fetch, write, copy_bytes)
     bench = json.loads(open(bench_json).read().strip().splitlines()[-1]) if bench_json else None
@@ -150,6 +169,8 @@ def summarize(trace, fetch, write, copy_bytes, bench_json, kernel_re, out, cmds)
         L.append(f"bench.py HIP-event average of the same launches: {r['avg_launch_us']} us, "
                  f"algorithmic {r['bytes_per_launch'] / 1e6:.1f} MB per launch ({r['achieved']} GB/s)")
     L.append("")
+    if sq:
+        L += _sq_table(sq, cmds[3])
     L.append(f"traffic_bytes_per_launch: {statistics.mean(sel_rd) + statistics.mean(sel_wr):.0f}")
     L.append(f"category: {cat}")
     L.append(f"source_sha256: {source_sha()}")
@@ -198,13 +219,15 @@ def main():
     ap.add_argument("--cmd-trace", required=True)
     ap.add_argument("--cmd-fetch")
     ap.add_argument("--cmd-write")
+    ap.add_argument("--sq", help="counter run of SQ counters (instruction counts) to tabulate")
+    ap.add_argument("--cmd-sq")
     a = ap.parse_args()
     if a.title:
         print(trace_summary(a.trace, a.title, a.cmd_trace, a.out, a.bench_json, a.fetch, a.write, a.copy_bytes,
                             a.cmd_fetch, a.cmd_write))
         return
     print(summarize(a.trace, a.fetch, a.write, a.copy_bytes, a.bench_json, a.kernel, a.out,
-                    (a.cmd_trace, a.cmd_fetch, a.cmd_write)))
+                    (a.cmd_trace, a.cmd_fetch, a.cmd_write, a.cmd_sq), sq=a.sq))
 
 
 if __name__ == "__main__":
