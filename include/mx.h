@@ -330,9 +330,13 @@ int mx_sources_project(mx_grid *g, int nsrc, int W, const int64_t *origins, cons
  * one dtype).  Every phase of a step of all grids is one launch over the
  * concatenated work items of the batch; with persistent = 1 all nsteps
  * steps of all grids run inside a single cooperative launch, in which
- * workgroups claim the work items of each phase from an atomic counter;
- * phases are separated by grid-wide barriers whose wait is bounded (a
- * time-out returns MX_EDEVICE).  Passes are at most sweeps_per_pass of the
+ * workgroups claim the work items of all steps and phases in order from an
+ * atomic counter and an item waits only until the previous phase of its own
+ * grid has completed (per-grid counters; no grid-wide barrier, so the items
+ * of other grids fill the tail of a phase); the wait is bounded (a
+ * time-out returns MX_EDEVICE).  In FP32 the front and the first sweep
+ * pass of a step run as one phase when that pass is 3..6 sweeps deep and
+ * not the last (both schedules).  Passes are at most sweeps_per_pass of the
  * first config deep (capped at 7); mx_batch_init with sweeps_per_pass = 0
  * times candidate pass depths and chunk lengths on workspace scratch
  * fields (the bound state is never touched), separately for the grouped
@@ -357,7 +361,8 @@ int mx_batch_get_plan(mx_batch *b, int *sweeps_per_pass, int *tiles_total, int *
 /* One schedule's tuned shape (persistent = 0 grouped, 1 persistent): the
    deepest pass (sweeps), the rows of a sweep work item's chunk and of a
    front work item's, and the work items of one step (front plus sweep
-   passes).  Any output pointer may be NULL.  Host only; MX_EINVAL for a
+   passes; in FP32 the front and the first pass run as one phase on the
+   front's items when that pass is 3..6 sweeps deep and not the last).  Any output pointer may be NULL.  Host only; MX_EINVAL for a
    NULL batch. */
 int mx_batch_get_schedule(mx_batch *b, int persistent, int *sweeps_per_pass, int *chunk_rows, int *front_rows,
                           int *items_per_step);

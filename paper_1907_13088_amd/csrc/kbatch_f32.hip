@@ -12,6 +12,13 @@ hipError_t launch_front<float>(const GridDesc<float> *d, int ng, const int *item
 }
 
 template <>
+hipError_t launch_front_sweep<float>(const GridDesc<float> *d, int ng, const int *items, int nitems, int L, int k,
+                                    int bin, hipStream_t s)
+{
+    return launch_front_sweep_impl<float>(d, ng, items, nitems, L, k, bin, s);
+}
+
+template <>
 hipError_t launch_sweep<float>(const GridDesc<float> *d, int ng, const int *items, int nitems, int L, int k,
                               bool first, bool last, int xin, int xout, hipStream_t s)
 {
@@ -25,12 +32,12 @@ int persistent_blocks<float>(int q)
 }
 
 template <>
-hipError_t launch_persistent<float>(const GridDesc<float> *d, int ng, const int *items_f, const int *items_s,
-                                   int Lf, int Ls, int nsteps, int q, int npass, int nlow, int bin0, unsigned *bar,
-                                   int *err, int nblocks, hipStream_t s)
+hipError_t launch_persistent<float>(const GridDesc<float> *d, int ng, const int *items_f, const int *items_s, int Lf, int Ls,
+                            int nsteps, int q, int npass, int nlow, int bin0, unsigned *cnt, int ndone, int *err,
+                            int fuse, hipStream_t s)
 {
-    return persist_disp<float, KMAX>(d, ng, items_f, items_s, Lf, Ls, nsteps, q, npass, nlow, bin0, bar, err,
-                                    nblocks, s);
+    return persist_disp<float, KMAX>(d, ng, items_f, items_s, Lf, Ls, nsteps, q, npass, nlow, bin0, cnt, ndone, err, fuse,
+                                 s);
 }
 
 }  // namespace batch2d

@@ -88,7 +88,8 @@ struct mx_batch {
     std::vector<int> bound;
     void *desc;                        // device GridDesc<T>[ng]
     int *items_f, *items_s;            // device prefix sums (ng + 1)
-    unsigned *bar;                     // device barrier counters
+    unsigned *cnt;                     // device: claim counter, then per-grid phase counters
+    int ncnt;                          // per-grid phase counters available (ng * (m + 1))
     int *err;                          // device error flag
     int spp, Lf, Ls;                   // grouped schedule: pass depth cap, chunk rows
     int pk, pLf, pLs;                  // persistent schedule: the same
@@ -175,17 +176,29 @@ int upload(mx_batch *b, bool scratch_fields, int k, int Lf, int Ls)
     return MX_OK;
 }
 
+// the front runs fused with the first pass (FP32, more than one pass, a
+// first pass of 3..6 sweeps: the depths the fused kernel is built for)
+template <typename T>
+bool fuse_first(int first, int npass)
+{
+    return sizeof(T) == 4 && npass >= 2 && first >= batch2d::FUSE_KMIN && first <= batch2d::FUSE_KMAX;
+}
+
 template <typename T>
 int grouped_steps(mx_batch *b, int nsteps, int bin0)
 {
     const GridDesc<T> *d = (const GridDesc<T> *)b->desc;
     std::vector<int> sz;
     pass_sizes(b->m, b->spp, sz);
+    const bool fuse = fuse_first<T>(sz[0], (int)sz.size());
     int bin = bin0;
     for (int s = 0; s < nsteps; s++) {
-        BCHK(batch2d::launch_front<T>(d, b->ng, b->items_f, b->nf, b->Lf, bin, b->stream));
+        if (fuse)
+            BCHK(batch2d::launch_front_sweep<T>(d, b->ng, b->items_f, b->nf, b->Lf, sz[0], bin, b->stream));
+        else
+            BCHK(batch2d::launch_front<T>(d, b->ng, b->items_f, b->nf, b->Lf, bin, b->stream));
         bin ^= 1;
-        for (size_t p = 0; p < sz.size(); p++) {
+        for (size_t p = fuse ? 1 : 0; p < sz.size(); p++) {
             const bool first = p == 0, last = p + 1 == sz.size();
             BCHK(batch2d::launch_sweep<T>(d, b->ng, b->items_s, b->ns, b->Ls, sz[p], first, last,
                                           (int)((p + 1) & 1), (int)(p & 1), b->stream));
@@ -199,28 +212,26 @@ int persistent_steps(mx_batch *b, int nsteps, int bin0)
 {
     int q, npass, nlow;
     persistent_shape(b->m, b->pk, &q, &npass, &nlow);
-    const int nb = batch2d::persistent_blocks<T>(q);
-    if (nb <= 0) return bfail(MX_EDEVICE, "no co-resident workgroups for the persistent batch kernel");
-    // the barrier's arrival counter runs over a whole launch: at most
-    // 2^32 - 1 arrivals (npass + 1 barriers per step) per launch
-    const long long per_step = (long long)nb * (npass + 1);
-    const int max_steps = (int)std::min<long long>(0x7fffffffLL, 0xffffffffLL / per_step);
-    // barrier counters and error flag start at zero (copies: no memset node
-    // in a captured stream); a time-out flagged in one launch makes the
-    // later ones leave at their first barrier
-    static const unsigned zero[4] = {0, 0, 0, 0};
-    BCHK(hipMemcpyAsync(b->err, zero, sizeof(int), hipMemcpyHostToDevice, b->stream));
+    const int fuse = fuse_first<T>(nlow > 0 ? q - 1 : q, npass) ? 1 : 0;
+    const int nph = 1 + npass - fuse;   // phases per step
+    // the claim counter runs over a whole launch: at most 2^31 - 1 items
+    const long long per_step = (long long)b->nf + (long long)(npass - fuse) * b->ns;
+    const int max_steps = (int)std::max(1LL, std::min<long long>(0x7fffffffLL, 0x7fffffffLL / per_step));
+    // the error flag starts at zero (a copy: no memset node in a captured
+    // stream); a time-out flagged in one launch makes the later ones leave
+    // at their first wait
+    static const int zero = 0;
+    BCHK(hipMemcpyAsync(b->err, &zero, sizeof(int), hipMemcpyHostToDevice, b->stream));
     for (int s0 = 0; s0 < nsteps; s0 += max_steps) {
         const int n = std::min(max_steps, nsteps - s0);
-        BCHK(hipMemcpyAsync(b->bar, zero, 3 * sizeof(unsigned), hipMemcpyHostToDevice, b->stream));
         BCHK(batch2d::launch_persistent<T>((const GridDesc<T> *)b->desc, b->ng, b->items_f, b->items_s, b->pLf,
-                                           b->pLs, n, q, npass, nlow, bin0 ^ (s0 & 1), b->bar, b->err, nb,
-                                           b->stream));
+                                           b->pLs, n, q, npass, nlow, bin0 ^ (s0 & 1), b->cnt, b->ng * nph, b->err,
+                                           fuse, b->stream));
     }
     int h = 0;
     BCHK(hipMemcpyAsync(&h, b->err, sizeof(int), hipMemcpyDeviceToHost, b->stream));
     BCHK(hipStreamSynchronize(b->stream));
-    if (h) return bfail(MX_EDEVICE, "persistent batch launch: grid barrier timed out");
+    if (h) return bfail(MX_EDEVICE, "persistent batch launch: a wait for the previous phase timed out");
     return MX_OK;
 }
 
@@ -446,7 +457,8 @@ int mx_batch_workspace_size(const mx_config *cfgs, int ngrids, size_t *bytes)
         tot += ARRAYS * up((size_t)cells(c) * (c.dtype == MX_F64 ? 8 : 4));
     }
     const size_t dsz = cfgs[0].dtype == MX_F64 ? sizeof(GridDesc<double>) : sizeof(GridDesc<float>);
-    tot += up(dsz * ngrids) + 2 * up(sizeof(int) * (ngrids + 1)) + up(4 * sizeof(unsigned)) + up(sizeof(int));
+    tot += up(dsz * ngrids) + 2 * up(sizeof(int) * (ngrids + 1)) + up(sizeof(int));
+    tot += up(sizeof(unsigned) * (1 + (size_t)ngrids * (cfgs[0].sweeps + 1)));
     *bytes = tot;
     return MX_OK;
 }
@@ -492,9 +504,9 @@ int mx_batch_init(const mx_config *cfgs, int ngrids, void *stream, void *workspa
     b->desc = p; p += up(dsz * ngrids);
     b->items_f = (int *)p; p += up(sizeof(int) * (ngrids + 1));
     b->items_s = (int *)p; p += up(sizeof(int) * (ngrids + 1));
-    b->bar = (unsigned *)p; p += up(4 * sizeof(unsigned));
-    b->err = (int *)p;
-    BCHK(hipMemsetAsync(b->bar, 0, 4 * sizeof(unsigned), b->stream));
+    b->err = (int *)p; p += up(sizeof(int));
+    b->cnt = (unsigned *)p;
+    b->ncnt = ngrids * (b->m + 1);
     b->spp = b->pk = cfgs[0].sweeps_per_pass > 0 ? std::min(cfgs[0].sweeps_per_pass, batch2d::KMAX) : 5;
     b->Lf = b->Ls = b->pLf = b->pLs = 64;
     b->tuned = false;
@@ -580,15 +592,19 @@ int mx_batch_get_schedule(mx_batch *b, int persistent, int *sweeps_per_pass, int
     if (chunk_rows) *chunk_rows = Ls;
     if (front_rows) *front_rows = Lf;
     if (items_per_step) {
-        // front items, then one set of sweep items per pass
+        // front items (with the first pass when it runs fused), then one
+        // set of sweep items per other pass
         std::vector<int> sz;
         pass_sizes(b->m, k, sz);
+        const bool f64 = b->dtype == MX_F64;
+        const size_t nsep = sz.size() - ((f64 ? fuse_first<double>(sz[0], (int)sz.size())
+                                              : fuse_first<float>(sz[0], (int)sz.size())) ? 1 : 0);
         const int wf = batch2d::front_width(), ws = cut_width(b->m, k);
         long long n = 0;
         for (const mx_config &c : b->cfg) {
             const long long nx = c.n[0], ny = c.n[1];
             n += ((nx + wf - 1) / wf) * ((ny + Lf - 1) / Lf);
-            n += (long long)sz.size() * ((nx + ws - 1) / ws) * ((ny + Ls - 1) / Ls);
+            n += (long long)nsep * ((nx + ws - 1) / ws) * ((ny + Ls - 1) / Ls);
         }
         *items_per_step = (int)std::min<long long>(n, 0x7fffffff);
     }

@@ -179,6 +179,12 @@ inline int front_width() { return STRIP - 32; }   // aligned front strips
 inline int sweep_width(int k) { return stream_width<STRIP>(k); }
 template <typename T>
 hipError_t launch_front(const GridDesc<T> *d, int ng, const int *items, int nitems, int L, int bin, hipStream_t s);
+// the front and the first pass of k sweeps (3..6, FP32) in one launch over
+// the front's items; writes iterate buffer 0
+template <typename T>
+hipError_t launch_front_sweep(const GridDesc<T> *d, int ng, const int *items, int nitems, int L, int k, int bin,
+                              hipStream_t s);
+constexpr int FUSE_KMIN = 3, FUSE_KMAX = 6;   // fused first-pass depths (FP32)
 template <typename T>
 hipError_t launch_sweep(const GridDesc<T> *d, int ng, const int *items, int nitems, int L, int k, bool first,
                         bool last, int xin, int xout, hipStream_t s);
@@ -188,12 +194,16 @@ constexpr int KMAX = 7;          // deepest batched pass (grouped or persistent)
 template <typename T>
 int persistent_blocks(int q);
 // all nsteps steps in one cooperative launch: per step the front, then npass
-// passes, the first nlow of q - 1 sweeps and the rest of q.  bar[0..2] and
-// *err must be zero at launch.
+// passes, the first nlow of q - 1 sweeps and the rest of q (fuse: the front
+// and the first pass as one phase; FP32, first pass 3..6 deep).  No
+// grid-wide barrier: each item waits for the previous phase of its own grid
+// only.  cnt[0 .. ndone] (the claim counter, then ndone = ng * phases per
+// step per-grid counters) is zeroed by the launch; *err must be zero at
+// launch.
 template <typename T>
 hipError_t launch_persistent(const GridDesc<T> *d, int ng, const int *items_f, const int *items_s, int Lf, int Ls,
-                             int nsteps, int q, int npass, int nlow, int bin0, unsigned *bar, int *err,
-                             int nblocks, hipStream_t s);
+                             int nsteps, int q, int npass, int nlow, int bin0, unsigned *cnt, int ndone, int *err,
+                             int fuse, hipStream_t s);
 }  // namespace batch2d
 
 // 2D launchers (k2d.hip)
