@@ -3,6 +3,6 @@
 
 namespace mx {
 template void small_tiles<float>(int, int, int *, int *);
-template int small_capacity<float>(bool);
+template int small_capacity<float>(bool, int);
 template hipError_t launch_small<float>(const SmallArgs<float> &, bool, hipStream_t);
 }  // namespace mx

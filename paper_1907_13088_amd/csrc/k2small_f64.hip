@@ -3,6 +3,6 @@
 
 namespace mx {
 template void small_tiles<double>(int, int, int *, int *);
-template int small_capacity<double>(bool);
+template int small_capacity<double>(bool, int);
 template hipError_t launch_small<double>(const SmallArgs<double> &, bool, hipStream_t);
 }  // namespace mx

@@ -18,11 +18,15 @@
 namespace mx {
 namespace small2d {
 
-using tile2d::NT;
-
+// Tile shape and threads per workgroup: 1024 threads on a 32 x 8 (FP64) or
+// 32 x 16 (FP32) tile, so that a pass of 8 sweeps (a 48 x 24 or 48 x 32
+// region) has one or two cells per thread and four waves per SIMD hide the
+// LDS round trips of a sweep (128^2 FP64 tolerance solve: 98 against 104 us
+// per step with 256 threads and every pass depth unrolled, 110 with 256
+// threads and the level loop)
 template <typename T> struct Tile;
-template <> struct Tile<double> { static constexpr int TX = 32, TY = 8; };
-template <> struct Tile<float> { static constexpr int TX = 32, TY = 16; };
+template <> struct Tile<double> { static constexpr int TX = 32, TY = 8, NT = 1024; };
+template <> struct Tile<float> { static constexpr int TX = 32, TY = 16, NT = 1024; };
 constexpr int PMAX = 4;   // filter passes
 constexpr int KMAX = 8;   // sweeps per pass
 
@@ -67,7 +71,7 @@ template <typename T, int P>
 __device__ __forceinline__ void front(const SmallArgs<T> &a, int s, int bx, int by, int wg, char *lds, double *sred,
                                       const T *const inc[3])
 {
-    constexpr int TX = Tile<T>::TX, TY = Tile<T>::TY;
+    constexpr int TX = Tile<T>::TX, TY = Tile<T>::TY, NT = Tile<T>::NT;
     constexpr int EX = TX + 3, EY = TY + 3, BX = TX + 2, BY = TY + 2, JX = TX + 2 * P, JY = TY + 2 * P;
     T(*sE)[EY][EX] = reinterpret_cast<T(*)[EY][EX]>(lds);
     T(*sB)[BY][BX] = reinterpret_cast<T(*)[BY][BX]>(lds + sizeof(T) * 3 * EY * EX);
@@ -169,7 +173,7 @@ __device__ __forceinline__ void front(const SmallArgs<T> &a, int s, int bx, int 
             ntm += (double)vz * vz;
         }
     }
-    tile2d::block_sum2(nte, ntm, sred);
+    tile2d::block_sum2<NT>(nte, ntm, sred);
     if (tid == 0) {
         a.partial[2 * wg] = nte;
         a.partial[2 * wg + 1] = ntm;
@@ -177,6 +181,7 @@ __device__ __forceinline__ void front(const SmallArgs<T> &a, int s, int bx, int 
 }
 
 // sum of the per-workgroup partials, the same in every workgroup
+template <int NT>
 __device__ __forceinline__ void reduce_partials(const double *partial, int nwg, double *sred, double *sdec,
                                                 double &ra, double &rb)
 {
@@ -185,7 +190,7 @@ __device__ __forceinline__ void reduce_partials(const double *partial, int nwg, 
         x += partial[2 * i];
         y += partial[2 * i + 1];
     }
-    tile2d::block_sum2(x, y, sred);
+    tile2d::block_sum2<NT>(x, y, sred);
     if (threadIdx.x == 0) { sdec[0] = x; sdec[1] = y; }
     __syncthreads();
     ra = sdec[0];
@@ -193,28 +198,22 @@ __device__ __forceinline__ void reduce_partials(const double *partial, int nwg, 
     __syncthreads();
 }
 
+// A pass of k <= KMAX sweeps: one code path for every depth (a level loop
+// over the region of KMAX), which keeps the kernel's registers those of one
+// pass instead of eight inlined depths
 template <typename T, int BLK, bool DELTA>
 __device__ __forceinline__ void sweep_k(const Coef<T> &c, const SweepArgs<T> &sa, int flags, int k, int bx, int by, int wg,
                         char *lds, double *sred)
 {
-    constexpr int TX = Tile<T>::TX, TY = Tile<T>::TY;
-    switch (k) {
-    case 1: tile2d::sweep_tile<T, BLK, 1, TX, TY, DELTA>(c, sa, flags, bx, by, wg, lds, sred); break;
-    case 2: tile2d::sweep_tile<T, BLK, 2, TX, TY, DELTA>(c, sa, flags, bx, by, wg, lds, sred); break;
-    case 3: tile2d::sweep_tile<T, BLK, 3, TX, TY, DELTA>(c, sa, flags, bx, by, wg, lds, sred); break;
-    case 4: tile2d::sweep_tile<T, BLK, 4, TX, TY, DELTA>(c, sa, flags, bx, by, wg, lds, sred); break;
-    case 5: tile2d::sweep_tile<T, BLK, 5, TX, TY, DELTA>(c, sa, flags, bx, by, wg, lds, sred); break;
-    case 6: tile2d::sweep_tile<T, BLK, 6, TX, TY, DELTA>(c, sa, flags, bx, by, wg, lds, sred); break;
-    case 7: tile2d::sweep_tile<T, BLK, 7, TX, TY, DELTA>(c, sa, flags, bx, by, wg, lds, sred); break;
-    default: tile2d::sweep_tile<T, BLK, 8, TX, TY, DELTA>(c, sa, flags, bx, by, wg, lds, sred); break;
-    }
+    constexpr int TX = Tile<T>::TX, TY = Tile<T>::TY, NT = Tile<T>::NT;
+    tile2d::sweep_tile<T, BLK, KMAX, TX, TY, DELTA, NT, true>(c, sa, flags, bx, by, wg, lds, sred, k);
 }
 
 // E += inc on the own tile (inc[q] null: component unchanged)
 template <typename T>
 __device__ __forceinline__ void add_increment(const SmallArgs<T> &a, int bx, int by, const T *const inc[3])
 {
-    constexpr int TX = Tile<T>::TX, TY = Tile<T>::TY;
+    constexpr int TX = Tile<T>::TX, TY = Tile<T>::TY, NT = Tile<T>::NT;
     const int nx = a.c.nx, ny = a.c.ny;
     for (int e = threadIdx.x; e < TX * TY; e += NT) {
         const int gx = bx * TX + e % TX, gy = by * TY + e / TX;
@@ -232,9 +231,13 @@ __device__ __forceinline__ void add_increment(const SmallArgs<T> &a, int bx, int
 // has read E (the front adds it on the fly for its tile and halo), right
 // after the barrier that ends that front and before the first sweep pass
 // can overwrite the iterate: no barrier of its own.
-template <typename T, bool DELTA>
-__global__ __launch_bounds__(NT) void k2_small(SmallArgs<T> a)
+// BLKS: the blocks the grid steps (1 TE, 2 TM, 3 both); a kernel holds the
+// sweep variants of those blocks only (as the active blocks of a two-block
+// grid change, 3 holds all three).
+template <typename T, bool DELTA, int BLKS>
+__global__ __launch_bounds__(Tile<T>::NT) void k2_small(SmallArgs<T> a)
 {
+    constexpr int NT = Tile<T>::NT;
     __shared__ __attribute__((aligned(16))) char lds[lds_bytes<T>()];
     __shared__ double sred[2 * NT / 64];
     __shared__ double sdec[2];
@@ -256,7 +259,7 @@ __global__ __launch_bounds__(NT) void k2_small(SmallArgs<T> a)
         add_increment(a, bx, by, inc);
         SmallStat st{};
         double r0, r1;
-        reduce_partials(a.partial, nwg, sred, sdec, r0, r1);
+        reduce_partials<NT>(a.partial, nwg, sred, sdec, r0, r1);
         st.rhsn[0] = (a.blocks & 1) ? sqrt(r0) : 0.0;
         st.rhsn[1] = (a.blocks & 2) ? sqrt(r1) : 0.0;
         bool active[2];
@@ -283,11 +286,17 @@ __global__ __launch_bounds__(NT) void k2_small(SmallArgs<T> a)
             sa.partial = a.partial;
             const int flags = (first ? SW_FIRST : 0) | SW_RESID | SW_STORE;
             const int act = (active[0] ? 1 : 0) | (active[1] ? 2 : 0);
-            if (act == 1) sweep_k<T, 1, DELTA>(c, sa, flags, kk, bx, by, wg, lds, sred);
-            else if (act == 2) sweep_k<T, 2, DELTA>(c, sa, flags, kk, bx, by, wg, lds, sred);
-            else sweep_k<T, 3, DELTA>(c, sa, flags, kk, bx, by, wg, lds, sred);
+            if constexpr (BLKS == 1) {
+                sweep_k<T, 1, DELTA>(c, sa, flags, kk, bx, by, wg, lds, sred);
+            } else if constexpr (BLKS == 2) {
+                sweep_k<T, 2, DELTA>(c, sa, flags, kk, bx, by, wg, lds, sred);
+            } else {
+                if (act == 1) sweep_k<T, 1, DELTA>(c, sa, flags, kk, bx, by, wg, lds, sred);
+                else if (act == 2) sweep_k<T, 2, DELTA>(c, sa, flags, kk, bx, by, wg, lds, sred);
+                else sweep_k<T, 3, DELTA>(c, sa, flags, kk, bx, by, wg, lds, sred);
+            }
             if (!grid_barrier(a.bar, nwg, a.err, &sflag)) return;
-            reduce_partials(a.partial, nwg, sred, sdec, r0, r1);
+            reduce_partials<NT>(a.partial, nwg, sred, sdec, r0, r1);
             const double r[2] = {sqrt(r0), sqrt(r1)};
             for (int b = 0; b < 2; b++) {
                 if (!active[b]) continue;
@@ -333,17 +342,29 @@ void small_tiles(int nx, int ny, int *ntx, int *nty)
     *nty = (ny + small2d::Tile<T>::TY - 1) / small2d::Tile<T>::TY;
 }
 
+namespace small2d {
 template <typename T>
-int small_capacity(bool delta)
+const void *kernel(bool delta, int blocks)
 {
-    static std::atomic<int> cache[2][MX_MAX_DEVICES];
-    return per_device(cache[delta ? 1 : 0], [&]() {
+    if (delta)
+        return blocks == 1 ? (const void *)k2_small<T, true, 1>
+               : blocks == 2 ? (const void *)k2_small<T, true, 2> : (const void *)k2_small<T, true, 3>;
+    return blocks == 1 ? (const void *)k2_small<T, false, 1>
+           : blocks == 2 ? (const void *)k2_small<T, false, 2> : (const void *)k2_small<T, false, 3>;
+}
+}  // namespace small2d
+
+template <typename T>
+int small_capacity(bool delta, int blocks)
+{
+    static std::atomic<int> cache[2][3][MX_MAX_DEVICES];
+    return per_device(cache[delta ? 1 : 0][blocks - 1], [&]() {
         int dev = 0, coop = 0, cu = 0, per = 0;
         if (hipGetDevice(&dev) != hipSuccess) return 0;
         if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
         if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-        const void *k = delta ? (const void *)small2d::k2_small<T, true> : (const void *)small2d::k2_small<T, false>;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, small2d::NT, 0) != hipSuccess) return 0;
+        const void *k = small2d::kernel<T>(delta, blocks);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, small2d::Tile<T>::NT, 0) != hipSuccess) return 0;
         return per * cu;
     });
 }
@@ -353,8 +374,8 @@ hipError_t launch_small(const SmallArgs<T> &a, bool delta, hipStream_t s)
 {
     void *args[] = {(void *)&a};
     const int nwg = a.ntx * a.nty;
-    const void *k = delta ? (const void *)small2d::k2_small<T, true> : (const void *)small2d::k2_small<T, false>;
-    return hipLaunchCooperativeKernel(k, dim3(nwg), dim3(small2d::NT), args, 0, s);
+    const void *k = small2d::kernel<T>(delta, a.blocks);
+    return hipLaunchCooperativeKernel(k, dim3(nwg), dim3(small2d::Tile<T>::NT), args, 0, s);
 }
 
 }  // namespace mx

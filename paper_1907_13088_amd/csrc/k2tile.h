@@ -27,7 +27,9 @@ template <> struct NComp<3> { static constexpr int n = 3; };
 template <int BLK>
 __device__ __forceinline__ constexpr int gq(int q) { return BLK == 2 ? 2 : q; }
 
-// Sum two doubles over the workgroup in a fixed order; valid in thread 0.
+// Sum two doubles over a workgroup of NTH threads in a fixed order; valid in
+// thread 0.
+template <int NTH = NT>
 __device__ __forceinline__ void block_sum2(double &a, double &b, double *sh)
 {
     for (int off = 32; off > 0; off >>= 1) {
@@ -40,7 +42,7 @@ __device__ __forceinline__ void block_sum2(double &a, double &b, double *sh)
     __syncthreads();
     if (threadIdx.x == 0) {
         a = 0.0; b = 0.0;
-        for (int i = 0; i < NT / 64; i++) { a += sh[2 * i]; b += sh[2 * i + 1]; }
+        for (int i = 0; i < NTH / 64; i++) { a += sh[2 * i]; b += sh[2 * i + 1]; }
     }
 }
 
@@ -55,15 +57,19 @@ constexpr size_t sweep_lds_bytes() { return sizeof(T) * 2 * NComp<BLK>::n * (TX 
 // interior is written back once.  Ping-pong LDS buffers, one barrier per
 // sweep.
 // ---------------------------------------------------------------------------
-// Tile (bx, by) of TX x TY output cells; `lds` holds sweep_lds_bytes bytes;
-// the FP64 partial norms (TE, TM) of the last sweep go to partial[2 wg].
-template <typename T, int BLK, int K, int TX, int TY, bool DELTA>
+// Tile (bx, by) of TX x TY output cells, NTH threads; `lds` holds
+// sweep_lds_bytes bytes; the FP64 partial norms (TE, TM) of the last sweep
+// go to partial[2 wg].  RUNTIME: the pass runs `levels` <= K sweeps in a
+// level loop that is not unrolled (one code path for every pass depth, on
+// the region of K; each cell's arithmetic is that of a pass of `levels`).
+template <typename T, int BLK, int K, int TX, int TY, bool DELTA, int NTH = NT, bool RUNTIME = false>
 __device__ __forceinline__ void sweep_tile(const Coef<T> &c, const SweepArgs<T> &a, int flags, int bx, int by,
-                                           size_t wg, void *lds, double *sred)
+                                           size_t wg, void *lds, double *sred, int levels = K)
 {
+    const int KL = RUNTIME ? levels : K;
     constexpr int NC = NComp<BLK>::n;
     constexpr int RX = TX + 2 * K, RY = TY + 2 * K, NR = RX * RY;
-    constexpr int NS = (NR + NT - 1) / NT;
+    constexpr int NS = (NR + NTH - 1) / NTH;
     constexpr bool TE = BLK & 1, TM = BLK & 2;
     T(*buf)[NC][NR] = reinterpret_cast<T(*)[NC][NR]>(lds);
 
@@ -75,7 +81,7 @@ __device__ __forceinline__ void sweep_tile(const Coef<T> &c, const SweepArgs<T> 
     T own[NS][NC];   // b (standard) at every owned cell; s (delta) at owned interior cells
 #pragma unroll
     for (int s = 0; s < NS; s++) {
-        const int cc = tid + NT * s;
+        const int cc = tid + NTH * s;
         if (cc >= NR) break;
         const int cy = cc / RX, cx = cc - cy * RX;
         const size_t o = (size_t)wrapi(ry0 + cy, ny) * nx + wrapi(rx0 + cx, nx);
@@ -91,13 +97,13 @@ __device__ __forceinline__ void sweep_tile(const Coef<T> &c, const SweepArgs<T> 
     }
     __syncthreads();
 
-#pragma unroll
-    for (int l = 1; l <= K; l++) {
+#pragma unroll(RUNTIME ? 1 : K)
+    for (int l = 1; l <= KL; l++) {
         const T *src = &buf[(l - 1) & 1][0][0];
         T *dst = &buf[l & 1][0][0];
 #pragma unroll
         for (int s = 0; s < NS; s++) {
-            const int cc = tid + NT * s;
+            const int cc = tid + NTH * s;
             if (cc >= NR) break;
             const int cy = cc / RX, cx = cc - cy * RX;
             if (cx < l || cx >= RX - l || cy < l || cy >= RY - l) continue;
@@ -138,12 +144,12 @@ __device__ __forceinline__ void sweep_tile(const Coef<T> &c, const SweepArgs<T> 
         __syncthreads();
     }
 
-    const T *fin = &buf[K & 1][0][0];
-    const T *prv = &buf[(K - 1) & 1][0][0];
+    const T *fin = &buf[KL & 1][0][0];
+    const T *prv = &buf[(KL - 1) & 1][0][0];
     double rte = 0.0, rtm = 0.0;
 #pragma unroll
     for (int s = 0; s < NS; s++) {
-        const int cc = tid + NT * s;
+        const int cc = tid + NTH * s;
         if (cc >= NR) break;
         const int cy = cc / RX, cx = cc - cy * RX;
         if (cx < K || cx >= K + TX || cy < K || cy >= K + TY) continue;
@@ -166,7 +172,7 @@ __device__ __forceinline__ void sweep_tile(const Coef<T> &c, const SweepArgs<T> 
         }
     }
     if (flags & SW_RESID) {
-        block_sum2(rte, rtm, sred);
+        block_sum2<NTH>(rte, rtm, sred);
         if (tid == 0) {
             a.partial[2 * wg] = rte;
             a.partial[2 * wg + 1] = rtm;

@@ -856,7 +856,7 @@ bool small_ok(const mx_grid *g)
     if (c.filter_passes > 4 || g->spp[0] < 1 || g->spp[0] > 8 || c.sweeps < 1 || !g->small_bar) return false;
     int ntx = 0, nty = 0;
     small_tiles<T>((int)c.n[0], (int)c.n[1], &ntx, &nty);
-    return (long long)ntx * nty <= small_capacity<T>(c.form == MX_FORM_DELTA) && (long long)ntx * nty <= max_wg(&c);
+    return (long long)ntx * nty <= small_capacity<T>(c.form == MX_FORM_DELTA, c.blocks) && (long long)ntx * nty <= max_wg(&c);
 }
 
 template <typename T>

@@ -270,7 +270,7 @@ struct SmallArgs {
 template <typename T>
 void small_tiles(int nx, int ny, int *ntx, int *nty);
 template <typename T>
-int small_capacity(bool delta);
+int small_capacity(bool delta, int blocks);
 template <typename T>
 hipError_t launch_small(const SmallArgs<T> &a, bool delta, hipStream_t s);
 
