@@ -423,6 +423,8 @@ def _run_3d(steps, warm, solver, form, dtype="f32"):
         "steps": steps, "ms_per_step": round(dt / steps * 1e3, 2), "mean_sweeps": round(sweeps, 1),
         "sweeps_per_pass": g_spp,
         "nonconverged_steps": sum(s.nonconverged[0] for s in st),
+        "front_us": round(1e3 * prof["front"]["ms"] / max(prof["front"]["launches"], 1), 1),
+        "front_GBps": round(prof["front"]["bytes"] / (prof["front"]["ms"] / 1e3) / 1e9, 1) if prof["front"]["ms"] else None,
         "sweep_pass_us": round(1e3 * sw["ms"] / max(sw["launches"], 1), 1),
         "sweep_pass_GBps": round(sw["bytes"] / (sw["ms"] / 1e3) / 1e9, 1) if sw["ms"] else None}
 

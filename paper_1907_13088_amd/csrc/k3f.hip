@@ -21,14 +21,22 @@
 namespace mx {
 namespace {
 
-constexpr int FX = 64, FY = 8, FT = FX * FY;
-constexpr int EX = FX + 3, EY = FY + 3, ECELLS = EX * EY;   // E tile: x, y in [-1, +2]
-constexpr int BX = FX + 2, BY = FY + 2, BCELLS = BX * BY;   // B^{n+1/2} tile: x, y in [-1, +1]
-constexpr int EPER = (ECELLS + FT - 1) / FT;
-constexpr int BPER = (BCELLS + FT - 1) / FT;
+// Tile of FX x FY columns, one thread each: FP32 64 x 16 (1024 threads; the
+// recomputed B^{n+1/2} halo is 16 % of the tile: 512^3, p = 1: 2.10 ms per
+// step against 2.41 with 64 x 8 and 2.60 with 32 x 32), FP64 64 x 8 (the LDS
+// of a 64 x 16 FP64 tile would exceed a CU's)
+template <typename T>
+struct Geo {
+    static constexpr int FX = 64, FY = sizeof(T) == 4 ? 16 : 8, FT = FX * FY;
+    static constexpr int EX = FX + 3, EY = FY + 3, ECELLS = EX * EY;   // E tile: x, y in [-1, +2]
+    static constexpr int BX = FX + 2, BY = FY + 2, BCELLS = BX * BY;   // B^{n+1/2} tile: x, y in [-1, +1]
+    static constexpr int EPER = (ECELLS + FT - 1) / FT;
+    static constexpr int BPER = (BCELLS + FT - 1) / FT;
+};
 
-template <int P>
+template <typename T, int P>
 struct JTile {
+    static constexpr int FX = Geo<T>::FX, FY = Geo<T>::FY, FT = Geo<T>::FT;
     static constexpr int JX = FX + 2 * P, JY = FY + 2 * P, CELLS = JX * JY;
     static constexpr int PER = (CELLS + FT - 1) / FT;     // raw current cells per thread
     static constexpr int XITEMS = FX * JY;                // x-filtered cells per component
@@ -68,10 +76,13 @@ __device__ __forceinline__ T binom_cascade(T (&v)[2 * P + 1])
 }
 
 template <typename T, int P>
-__global__ __launch_bounds__(FT) void k3_front(Coef<T> c, FrontArgs<T> a, const T *Bx_in, const T *By_in,
-                                               const T *Bz_in, int Lz)
+__global__ __launch_bounds__(Geo<T>::FT) void k3_front(Coef<T> c, FrontArgs<T> a, const T *Bx_in, const T *By_in,
+                                                       const T *Bz_in, int Lz)
 {
-    using JT = JTile<P>;
+    using G = Geo<T>;
+    constexpr int FX = G::FX, FY = G::FY, FT = G::FT, EX = G::EX, EY = G::EY, ECELLS = G::ECELLS;
+    constexpr int BX = G::BX, BY = G::BY, BCELLS = G::BCELLS, EPER = G::EPER, BPER = G::BPER;
+    using JT = JTile<T, P>;
     __shared__ T sE[2][3][EY][EX];
     __shared__ T sB[3][3][BY][BX];
     __shared__ T sJ[3][JT::JY][JT::JX];
@@ -290,16 +301,27 @@ hipError_t launch_front3d(const Coef<T> &c, int filter_passes, const FrontArgs<T
 {
     if (filter_passes < 0 || filter_passes > 2) return hipErrorInvalidValue;
     const int p = a.J0[0] ? filter_passes : 0;
-    // z chunks: enough workgroups for two per CU, each chunk at least 16 planes
-    const int gx = (c.nx + FX - 1) / FX, gy = (c.ny + FY - 1) / FY;
-    int nzc = std::max(1, std::min(c.nz / 16, (512 + gx * gy - 1) / (gx * gy)));
+    using G = Geo<T>;
+    const void *k = p == 0 ? (const void *)k3_front<T, 0> : p == 1 ? (const void *)k3_front<T, 1>
+                                                                   : (const void *)k3_front<T, 2>;
+    // z chunks: one round of the resident workgroups, each chunk at least 16 planes
+    static std::atomic<int> resident[3][MX_MAX_DEVICES];
+    const int slots = per_device(resident[p], [k] {
+        int o = 0, dev = 0, cu = 0;
+        (void)hipGetDevice(&dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k, G::FT, 0) != hipSuccess || o < 1) o = 1;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu < 1) cu = 256;
+        return o * cu;
+    });
+    const int gx = (c.nx + G::FX - 1) / G::FX, gy = (c.ny + G::FY - 1) / G::FY;
+    int nzc = std::max(1, std::min(c.nz / 16, (slots + gx * gy - 1) / (gx * gy)));
     const int Lz = (c.nz + nzc - 1) / nzc;
     nzc = (c.nz + Lz - 1) / Lz;
     dim3 g(gx, gy, nzc);
     *nwg = g.x * g.y * g.z;
-    if (p == 0) hipLaunchKernelGGL((k3_front<T, 0>), g, dim3(FT), 0, s, c, a, Bin[0], Bin[1], Bin[2], Lz);
-    else if (p == 1) hipLaunchKernelGGL((k3_front<T, 1>), g, dim3(FT), 0, s, c, a, Bin[0], Bin[1], Bin[2], Lz);
-    else hipLaunchKernelGGL((k3_front<T, 2>), g, dim3(FT), 0, s, c, a, Bin[0], Bin[1], Bin[2], Lz);
+    if (p == 0) hipLaunchKernelGGL((k3_front<T, 0>), g, dim3(G::FT), 0, s, c, a, Bin[0], Bin[1], Bin[2], Lz);
+    else if (p == 1) hipLaunchKernelGGL((k3_front<T, 1>), g, dim3(G::FT), 0, s, c, a, Bin[0], Bin[1], Bin[2], Lz);
+    else hipLaunchKernelGGL((k3_front<T, 2>), g, dim3(G::FT), 0, s, c, a, Bin[0], Bin[1], Bin[2], Lz);
     return hipGetLastError();
 }
 
