@@ -158,7 +158,13 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
     const unsigned allb = rowb * (unsigned)ny;
     const unsigned colb = (unsigned)gx * (unsigned)sizeof(T);
     const int tbeg = Y0 - K, tend = Y0 + L + 2 * K;
-    unsigned lo = (unsigned)wrapi(tbeg, ny) * rowb;
+    // Every step runs in the steady form (all levels, no row-range tests) in
+    // groups of 6 from the even step at or before tbeg: a level's value for a
+    // row outside its range feeds only rows outside the next level's range,
+    // and every store and E load tests its row.  (Steps with range tests
+    // took 2.8 times the instructions of a steady step.)
+    const int tstart = tbeg - (tbeg & 1);
+    unsigned lo = (unsigned)wrapi(tstart, ny) * rowb;
     auto load_row = [&](T(&x)[3], T(&cc)[3], T(&dd)[3]) {
         const unsigned o = lo + colb;
 #pragma unroll
@@ -188,7 +194,7 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
 #pragma unroll
     for (int u = 0; u < PF; u++) {
         load_row(px[u], pc[u], pd[u]);
-        load_e(tbeg + u - 2 * K, pe[u]);
+        load_e(tstart + u - 2 * K, pe[u]);
     }
     double rte = 0.0, rtm = 0.0;
 
@@ -296,8 +302,7 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
                     if (BOTH) *reinterpret_cast<Triple<T> *>(&xq[l][pw][i + 1]) = Triple<T>{nv[1], nv[2], nv[0]};
                     else if (TE) xp[l][pw][i + 1] = Pair<T>{nv[0], nv[1]};
                     else xz[l][pw][i + 1] = nv[2];
-                } else if (outcol && (ALL ? r < rend : (r >= Y0 && r < rend))) {
-                    // (in the steady state r >= Y0 holds: t >= Y0 + 2K)
+                } else if (outcol && r >= Y0 && r < rend) {
                     const unsigned o = (unsigned)(r * nx + gxi) * (unsigned)sizeof(T);
                     if (resid) {
                         if (TE) {
@@ -352,17 +357,10 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
         }
         lds_barrier();
     };
-    // a step outside the steady state (set index and LDS buffer at run time)
-    auto step_edge = [&](const int t) { step(t, std::false_type{}, std::integral_constant<int, 0>{}); };
-
-    // fill, steady state (every level active), drain
-    const int ts0 = Y0 + 2 * K, ts1 = Y0 + L + K;
-    int t = tbeg;
-    using A = std::true_type;
-    for (; (t < ts0 || (t & 1)) && t < tend; t++) step_edge(t);
     // groups of 6 steps: a multiple of the window periods (2 and 3), of the
     // LDS double buffer and of the prefetch depth
-    for (; t + 6 <= ts1; t += 6) {
+    using A = std::true_type;
+    for (int t = tstart; t < tend; t += 6) {
         step(t + 0, A{}, std::integral_constant<int, 0>{});
         step(t + 1, A{}, std::integral_constant<int, 1>{});
         step(t + 2, A{}, std::integral_constant<int, 2>{});
@@ -370,7 +368,6 @@ __device__ __forceinline__ void stream_tile(const Coef<T> &c, const SweepArgs<T>
         step(t + 4, A{}, std::integral_constant<int, 4>{});
         step(t + 5, A{}, std::integral_constant<int, 5>{});
     }
-    for (; t < tend; t++) step_edge(t);
     if (resid) {
         block_sum2<RX>(rte, rtm, sred);
         if (threadIdx.x == 0) {
