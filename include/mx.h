@@ -106,9 +106,10 @@ typedef struct mx_config {
     int form;             /* MX_FORM_STANDARD or MX_FORM_DELTA */
     int sweeps_per_pass;  /* sweeps fused per pass over HBM, in [0, 16]; 0 = library
                              choice.  Row streaming (2D) caps it at the deepest
-                             kernel built: both blocks together 7 (FP32), 3 (FP64),
-                             delta form 6, 3; per block TE 10 (FP32), 5 (FP64),
-                             delta 9, 4; TM 16 (FP32), 8 (FP64).  LDS tile: <= 8.
+                             kernel built: both blocks together 9 (FP32), 4 (FP64),
+                             delta form 8, 3; per block TE 14 (FP32), 7 (FP64),
+                             delta 12, 6; TM 16 (FP32), 12 (FP64), delta 16, 10.
+                             LDS tile: <= 8.
                              3D: up to 3 in FP32, 2 in FP64 (library choice: the
                              most allowed). */
     int variant;          /* 2D sweep kernel: 0 library choice (FP32: 4, FP64 and
@@ -126,8 +127,8 @@ typedef struct mx_config {
                              steps run as in 2) */
     int solver;           /* MX_SOLVER_ALG1 (default) or MX_SOLVER_CHEBYSHEV (2D,
                              and 3D with cubic cells); the
-                             2D Chebyshev passes fuse at most: both blocks 5
-                             (FP32), 2 (FP64); TE 8, 3; TM 12, 6 */
+                             2D Chebyshev passes fuse at most: both blocks 6
+                             (FP32), 2 (FP64); TE 10, 4; TM 16, 8 */
 } mx_config;
 
 typedef struct mx_step_stats {

@@ -34,13 +34,9 @@ hipError_t launch_form(const Coef<T> &c, int block, int k, int flags, const Swee
 int stream2d_kmax(bool f64, int block, int form)
 {
     // must agree with stream2d::stream_kmax
-    if (form == FM_CHEB) {
-        if (!f64) return block == 1 ? 8 : block == 2 ? 12 : 5;
-        return block == 1 ? 3 : block == 2 ? 6 : 2;
-    }
-    const bool delta = form == FM_DELTA;
-    if (!f64) return block == 1 ? (delta ? 9 : 10) : block == 2 ? 16 : (delta ? 6 : 7);
-    return block == 1 ? (delta ? 4 : 5) : block == 2 ? 8 : 3;
+    if (form == FM_CHEB) return !f64 ? (block == 1 ? 10 : block == 2 ? 16 : 6) : (block == 1 ? 4 : block == 2 ? 8 : 2);
+    if (form == FM_DELTA) return !f64 ? (block == 1 ? 12 : block == 2 ? 16 : 8) : (block == 1 ? 6 : block == 2 ? 10 : 3);
+    return !f64 ? (block == 1 ? 14 : block == 2 ? 16 : 9) : (block == 1 ? 7 : block == 2 ? 12 : 4);
 }
 
 template <typename T>

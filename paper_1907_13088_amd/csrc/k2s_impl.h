@@ -428,15 +428,16 @@ hipError_t stream_k(const Coef<T> &c, int flags, const SweepArgs<T> &a, hipStrea
 
 // deepest pass (sweeps per pass) of a block set's kernel: the per-level
 // register windows must leave two waves per SIMD (TE carries 2 components,
-// TM one, both together 3; the Chebyshev form carries one more value per
-// component and level)
+// TM one, both together 3; the delta and Chebyshev forms carry one more
+// value per component and level); TM is capped at 16, the levels of the
+// per-sweep factor table
 template <typename T, int BLK, int FORM>
 constexpr int stream_kmax()
 {
-    if (FORM == FM_CHEB)
-        return sizeof(T) == 4 ? (BLK == 1 ? 8 : BLK == 2 ? 12 : 5) : (BLK == 1 ? 3 : BLK == 2 ? 6 : 2);
-    constexpr bool DELTA = FORM == FM_DELTA;
-    return sizeof(T) == 4 ? (BLK == 1 ? (DELTA ? 9 : 10) : BLK == 2 ? 16 : (DELTA ? 6 : 7)) : (BLK == 1 ? (DELTA ? 4 : 5) : BLK == 2 ? 8 : 3);
+    constexpr bool F32 = sizeof(T) == 4;
+    if (FORM == FM_CHEB) return F32 ? (BLK == 1 ? 10 : BLK == 2 ? 16 : 6) : (BLK == 1 ? 4 : BLK == 2 ? 8 : 2);
+    if (FORM == FM_DELTA) return F32 ? (BLK == 1 ? 12 : BLK == 2 ? 16 : 8) : (BLK == 1 ? 6 : BLK == 2 ? 10 : 3);
+    return F32 ? (BLK == 1 ? 14 : BLK == 2 ? 16 : 9) : (BLK == 1 ? 7 : BLK == 2 ? 12 : 4);
 }
 
 template <typename T, int BLK, int FORM, int K>

@@ -51,14 +51,14 @@ def test_te_planewave_fp64_tolerance_replay_and_decisions():
 
 # deepest FP64 streaming pass (TE, TM), standard form: both blocks in one
 # pass, or each block on its own
-KMAX_F64 = {mx.VARIANT_STREAM: (3, 3), mx.VARIANT_STREAM_BLOCK: (5, 8)}
+KMAX_F64 = {mx.VARIANT_STREAM: (4, 4), mx.VARIANT_STREAM_BLOCK: (7, 12)}
 VARIANTS = [mx.VARIANT_TILE, mx.VARIANT_STREAM, mx.VARIANT_STREAM_BLOCK]
 
 
 # the LDS-tile kernel fuses at most 8 sweeps; the joint FP64 streaming pass
-# caps at 3, so 4 already exercises the cap
-DEPTHS = ([(mx.VARIANT_TILE, k) for k in range(1, 9)] + [(mx.VARIANT_STREAM, k) for k in range(1, 5)]
-          + [(mx.VARIANT_STREAM_BLOCK, k) for k in (1, 2, 3, 4, 5, 6, 7, 8, 16)])
+# caps at 4, so 5 already exercises the cap; per block TE caps at 7, TM at 12
+DEPTHS = ([(mx.VARIANT_TILE, k) for k in range(1, 9)] + [(mx.VARIANT_STREAM, k) for k in range(1, 6)]
+          + [(mx.VARIANT_STREAM_BLOCK, k) for k in (1, 2, 3, 4, 5, 6, 7, 8, 12, 16)])
 
 
 @pytest.mark.parametrize("variant,spp", DEPTHS)

@@ -17,7 +17,7 @@ from gpu_helpers import gpu_config, log, rel_err, run_gpu, run_oracle
 pytestmark = pytest.mark.gpu
 CHEB = mx.SOLVER_CHEBYSHEV
 # deepest Chebyshev pass (TE, TM) in FP64: both blocks in one pass, each on its own
-KMAX_F64 = {mx.VARIANT_STREAM: (2, 2), mx.VARIANT_STREAM_BLOCK: (3, 6)}
+KMAX_F64 = {mx.VARIANT_STREAM: (2, 2), mx.VARIANT_STREAM_BLOCK: (4, 8)}
 
 
 @pytest.fixture(scope="module")
@@ -29,7 +29,7 @@ def small_modes():
 @pytest.mark.parametrize("variant,spp", [(mx.VARIANT_STREAM, 1), (mx.VARIANT_STREAM, 2),
                                          (mx.VARIANT_STREAM_BLOCK, 1), (mx.VARIANT_STREAM_BLOCK, 2),
                                          (mx.VARIANT_STREAM_BLOCK, 3), (mx.VARIANT_STREAM_BLOCK, 6),
-                                         (mx.VARIANT_STREAM_BLOCK, 0)])
+                                         (mx.VARIANT_STREAM_BLOCK, 8), (mx.VARIANT_STREAM_BLOCK, 0)])
 def test_cheb_fp64_fixed_m_every_pass_depth(small_modes, variant, spp):
     w = small_modes
     nsteps = 8
