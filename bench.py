@@ -240,7 +240,7 @@ def main():
                         f"first {depths[0]} sweeps (stores B, dE' and the iterate)",
                         FRONT_FLOPS + SWEEP_FLOPS * depths[0],
                         "row streaming with one LDS exchange and barrier per row step, two waves per SIMD "
-                        "(254 VGPRs): the sweep levels' latency chain overlaps the front's HBM streams"),
+                        "(226 VGPRs): the sweep levels' latency chain overlaps the front's HBM streams"),
         "sweep": (f"k2_stream<float,3,K> row-streaming sweep passes storing their iterate "
                   f"(K = {'+'.join(map(str, store))})",
                   SWEEP_FLOPS * sum(store) / max(len(store), 1),
@@ -327,7 +327,8 @@ def main():
         "config": {"workload": f"2D periodic {n}x{n} TE+TM FP32, Courant 0.5, 256 Fourier modes |k|<=pi/2, "
                                f"64 Gaussian current pulses, 3-pass binomial filter, m=20 sweeps",
                    "grid": [n, n], "sweeps": w.sweeps, "filter_passes": w.filter_passes,
-                   "sweeps_per_pass": list(g32.block_sweeps_per_pass), "parallelism": "single GPU"},
+                   "sweeps_per_pass": list(g32.block_sweeps_per_pass), "pass_depths": depths,
+                   "front_fused": fused, "parallelism": "single GPU"},
         "fp64": fp64,
         "roofline": roofline,
         "kernels": kernels,

@@ -40,7 +40,7 @@ __device__ __forceinline__ bool grid_barrier(unsigned *bar, unsigned nblocks, in
             // arrived at this barrier, this one included
             while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
                 __builtin_amdgcn_s_sleep(2);
-                if (++spins > (1u << 25)) {   // about two seconds
+                if (++spins > (1u << 25)) {   // the sleeps alone: over 1.8 s at 2.4 GHz
                     __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     ok = 0;
                     break;

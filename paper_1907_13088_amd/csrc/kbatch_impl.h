@@ -206,7 +206,8 @@ __global__ __launch_bounds__(RX, sizeof(T) == 4 ? 2 : 1) void kb_persistent(cons
                 unsigned spins = 0;
                 while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
                     __builtin_amdgcn_s_sleep(2);
-                    // two device-scope loads per poll (about 2 us): a few seconds
+                    // 2^21 polls: over 0.1 s of sleep alone (2 x 64 cycles per poll)
+                    // plus two device-scope loads each, against an item's sub-ms run
                     if (++spins > (1u << 21) ||
                         __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
                         __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
