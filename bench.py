@@ -240,7 +240,7 @@ def main():
                         f"first {depths[0]} sweeps (stores B, dE' and the iterate)",
                         FRONT_FLOPS + SWEEP_FLOPS * depths[0],
                         "row streaming with one LDS exchange and barrier per row step, two waves per SIMD "
-                        "(226 VGPRs): the sweep levels' latency chain overlaps the front's HBM streams"),
+                        "(234 VGPRs): the sweep levels' latency chain overlaps the front's HBM streams"),
         "sweep": (f"k2_stream<float,3,K> row-streaming sweep passes storing their iterate "
                   f"(K = {'+'.join(map(str, store))})",
                   SWEEP_FLOPS * sum(store) / max(len(store), 1),

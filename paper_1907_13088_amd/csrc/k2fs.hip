@@ -18,7 +18,7 @@ MX_FS_EXTERN(6)
 #undef MX_FS_EXTERN
 }  // namespace fused2d
 
-bool front_sweep2d_ok(bool f64, int k, int p) { return !f64 && k >= 3 && k <= 6 && p >= 0 && p <= 4 && !(k == 6 && p == 4); }
+bool front_sweep2d_ok(bool f64, int k, int p) { return !f64 && k >= 3 && k <= 6 && p >= 0 && p <= 4; }
 
 template <>
 hipError_t launch_front_sweep2d<float>(const Coef<float> &c, int p, int k, const FrontArgs<float> &fa,

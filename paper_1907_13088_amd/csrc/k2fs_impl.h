@@ -338,21 +338,19 @@ hipError_t fs_launch(const Coef<T> &c, const FrontArgs<T> &fa, const T *const Bi
 
 // Launch shape: 256 columns per strip, 128-byte aligned output runs of 224
 // columns (the pass is bound by HBM traffic more than the deep sweep passes
-// are), one row in flight per thread (two would take more than the 256
-// registers of two waves per SIMD: 1.0 ms/step slower measured with spills)
+// are), two rows in flight per thread (4096^2, p = 3, K = 6: 281 against
+// 287 us with one, 283 with three; 234 and 246 VGPRs, two waves per SIMD)
 template <int K>
 hipError_t fs_dispatch_k(const Coef<float> &c, int p, const FrontArgs<float> &fa, const float *const Bin[3],
                          const SweepArgs<float> &sa, hipStream_t s, int *nwg)
 {
-    if (fa.J0[0] == nullptr) return fs_launch<float, 0, K, 256, false, true, 1, 2>(c, fa, Bin, sa, s, nwg);
+    if (fa.J0[0] == nullptr) return fs_launch<float, 0, K, 256, false, true, 2, 2>(c, fa, Bin, sa, s, nwg);
     switch (p) {
-    case 0: return fs_launch<float, 0, K, 256, true, true, 1, 2>(c, fa, Bin, sa, s, nwg);
-    case 1: return fs_launch<float, 1, K, 256, true, true, 1, 2>(c, fa, Bin, sa, s, nwg);
-    case 2: return fs_launch<float, 2, K, 256, true, true, 1, 2>(c, fa, Bin, sa, s, nwg);
-    case 3: return fs_launch<float, 3, K, 256, true, true, 1, 2>(c, fa, Bin, sa, s, nwg);
-    case 4:
-        if constexpr (K < 6) return fs_launch<float, 4, K, 256, true, true, 1, 2>(c, fa, Bin, sa, s, nwg);
-        return hipErrorInvalidValue;   // 6 sweeps and a 4-pass filter exceed the registers
+    case 0: return fs_launch<float, 0, K, 256, true, true, 2, 2>(c, fa, Bin, sa, s, nwg);
+    case 1: return fs_launch<float, 1, K, 256, true, true, 2, 2>(c, fa, Bin, sa, s, nwg);
+    case 2: return fs_launch<float, 2, K, 256, true, true, 2, 2>(c, fa, Bin, sa, s, nwg);
+    case 3: return fs_launch<float, 3, K, 256, true, true, 2, 2>(c, fa, Bin, sa, s, nwg);
+    case 4: return fs_launch<float, 4, K, 256, true, true, 2, 2>(c, fa, Bin, sa, s, nwg);
     default: return hipErrorInvalidValue;
     }
 }
