@@ -21,17 +21,24 @@
 namespace mx {
 namespace {
 
-// Tile of FX x FY columns, one thread each: FP32 64 x 16 (1024 threads; the
-// recomputed B^{n+1/2} halo is 16 % of the tile: 512^3, p = 1: 2.10 ms per
-// step against 2.41 with 64 x 8 and 2.60 with 32 x 32), FP64 64 x 8 (the LDS
-// of a 64 x 16 FP64 tile would exceed a CU's)
+// Tile of FX x FY columns, one thread each: FP32 128 x 8 (1024 threads),
+// FP64 64 x 8 (the LDS of a 1024-thread FP64 tile would exceed a CU's).
+// 512^3 FP32, p = 1, one plane in flight: 128 x 8 took 1.98 ms per step
+// against 2.10 with 64 x 16, 2.41 with 64 x 8 and 2.60 with 32 x 32: rows
+// of 128 columns touch 6 cache lines for 4 useful ones (64 columns: 4 for
+// 2), which outweighs the larger recomputed B^{n+1/2} halo (27 % of the
+// tile against 16 %).
 template <typename T>
 struct Geo {
-    static constexpr int FX = 64, FY = sizeof(T) == 4 ? 16 : 8, FT = FX * FY;
+    static constexpr int FX = sizeof(T) == 4 ? 128 : 64, FY = 8, FT = FX * FY;
     static constexpr int EX = FX + 3, EY = FY + 3, ECELLS = EX * EY;   // E tile: x, y in [-1, +2]
     static constexpr int BX = FX + 2, BY = FY + 2, BCELLS = BX * BY;   // B^{n+1/2} tile: x, y in [-1, +1]
     static constexpr int EPER = (ECELLS + FT - 1) / FT;
     static constexpr int BPER = (BCELLS + FT - 1) / FT;
+    // planes in flight per thread: FP32 two (1.87 against 1.98 ms; 128
+    // VGPRs, a few bytes spilled at p >= 1), FP64 one (two measured slower:
+    // 5.7 against 4.9 ms)
+    static constexpr int PF = sizeof(T) == 4 ? 2 : 1;
 };
 
 template <typename T, int P>
@@ -102,15 +109,15 @@ __global__ __launch_bounds__(Geo<T>::FT) void k3_front(Coef<T> c, FrontArgs<T> a
     const T *Bin[3] = {Bx_in, By_in, Bz_in};
 
     // tile cells of this thread, fixed for the whole march
-    size_t eoff[EPER];
+    unsigned eoff[EPER];
     int eidx[EPER];
     for (int u = 0; u < EPER; u++) {
         const int idx = tid + u * FT;
         eidx[u] = idx < ECELLS ? idx : -1;
         const int ix = idx % EX, iy = idx / EX;
-        eoff[u] = (size_t)wrapm(Y0 - 1 + iy, ny) * nx + wrapm(X0 - 1 + ix, nx);
+        eoff[u] = (unsigned)wrapm(Y0 - 1 + iy, ny) * (unsigned)nx + wrapm(X0 - 1 + ix, nx);
     }
-    size_t boff[BPER];
+    unsigned boff[BPER];
     int bidx[BPER];
     bool bown[BPER];
     for (int u = 0; u < BPER; u++) {
@@ -118,40 +125,47 @@ __global__ __launch_bounds__(Geo<T>::FT) void k3_front(Coef<T> c, FrontArgs<T> a
         bidx[u] = idx < BCELLS ? idx : -1;
         const int ix = idx % BX, iy = idx / BX;
         const int gx = X0 - 1 + ix, gy = Y0 - 1 + iy;
-        boff[u] = (size_t)wrapm(gy, ny) * nx + wrapm(gx, nx);
+        boff[u] = (unsigned)wrapm(gy, ny) * (unsigned)nx + wrapm(gx, nx);
         bown[u] = bidx[u] >= 0 && ix >= 1 && ix <= FX && iy >= 1 && iy <= FY && gx < nx && gy < ny;
     }
-    size_t joff[JT::PER];
+    unsigned joff[JT::PER];
     int jidx[JT::PER];
     for (int u = 0; u < JT::PER; u++) {
         const int idx = tid + u * FT;
         jidx[u] = (has_j && idx < JT::CELLS) ? idx : -1;
         const int ix = idx % JT::JX, iy = idx / JT::JX;
-        joff[u] = (size_t)wrapm(Y0 - P + iy, ny) * nx + wrapm(X0 - P + ix, nx);
+        joff[u] = (unsigned)wrapm(Y0 - P + iy, ny) * (unsigned)nx + wrapm(X0 - P + ix, nx);
     }
     const bool out = X0 + tx < nx && Y0 + ty < ny;
-    const size_t own = out ? (size_t)(Y0 + ty) * nx + (X0 + tx) : 0;
+    const unsigned own = out ? (unsigned)(Y0 + ty) * (unsigned)nx + (unsigned)(X0 + tx) : 0u;
 
-    // prefetched planes (registers)
-    T eP[EPER][3], bP[BPER][3], jP[JT::PER][3];
-    auto fetchE = [&](int k) {
+    // prefetched planes (registers): a ring of PF sets, set (t - t0) % PF
+    // holds what march step t stages
+    constexpr int PF = G::PF;
+    T eP[PF][EPER][3], bP[PF][BPER][3], jP[PF][JT::PER][3];
+    auto fetchE = [&](int k, auto st) {
+        constexpr int S = decltype(st)::value;
         const size_t zo = (size_t)wrapm(k, nz) * plane;
         for (int u = 0; u < EPER; u++)
             if (eidx[u] >= 0)
-                for (int q = 0; q < 3; q++) eP[u][q] = a.E[q][zo + eoff[u]];
+                for (int q = 0; q < 3; q++) eP[S][u][q] = a.E[q][zo + eoff[u]];
     };
-    auto fetchB = [&](int k) {
+    auto fetchB = [&](int k, auto st) {
+        constexpr int S = decltype(st)::value;
         const size_t zo = (size_t)wrapm(k, nz) * plane;
         for (int u = 0; u < BPER; u++)
             if (bidx[u] >= 0)
-                for (int q = 0; q < 3; q++) bP[u][q] = Bin[q][zo + boff[u]];
+                for (int q = 0; q < 3; q++) bP[S][u][q] = Bin[q][zo + boff[u]];
     };
-    auto fetchJ = [&](int k) {
+    auto fetchJ = [&](int k, auto st) {
+        constexpr int S = decltype(st)::value;
         const size_t zo = (size_t)wrapm(k, nz) * plane;
         for (int u = 0; u < JT::PER; u++)
             if (jidx[u] >= 0)
-                for (int q = 0; q < 3; q++) jP[u][q] = a.J0[q][zo + joff[u]];
+                for (int q = 0; q < 3; q++) jP[S][u][q] = a.J0[q][zo + joff[u]];
     };
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, PF - 1>;
 
     // z filter of the own column: level r keeps its two previous inputs
     T zin[P > 0 ? P : 1][2][3];
@@ -164,27 +178,42 @@ __global__ __launch_bounds__(Geo<T>::FT) void k3_front(Coef<T> c, FrontArgs<T> a
     // t0 fills the z filter (2P steps) and the B^{n+1/2} planes below Z0.
     const int t0 = min(Z0 - 1, Z0 + 2 - 2 * P);
     double acc = 0.0;
-    fetchE(t0);
-    fetchB(t0 - 1);
-    if (has_j) fetchJ(t0 - 2 + P);
-    for (int t = t0; t <= Z1 + 1; t++) {
+    fetchE(t0, S0{});
+    fetchB(t0 - 1, S0{});
+    if (has_j) fetchJ(t0 - 2 + P, S0{});
+    if constexpr (PF == 2) {
+        fetchE(t0 + 1, S1{});
+        fetchB(t0, S1{});
+        if (has_j) fetchJ(t0 - 1 + P, S1{});
+    }
+    auto body = [&](const int t, auto st) {
+        constexpr int S = decltype(st)::value;
         const int se = (t - t0) & 1, sep = se ^ 1;          // E slots of planes t and t - 1
         // --- stage plane t of E and the raw current plane t - 2 + P
         for (int u = 0; u < EPER; u++)
             if (eidx[u] >= 0)
-                for (int q = 0; q < 3; q++) (&sE[se][q][0][0])[eidx[u]] = eP[u][q];
+                for (int q = 0; q < 3; q++) (&sE[se][q][0][0])[eidx[u]] = eP[S][u][q];
         for (int u = 0; u < JT::PER; u++)
             if (jidx[u] >= 0)
-                for (int q = 0; q < 3; q++) (&sJ[q][0][0])[jidx[u]] = jP[u][q];
-        T bold[BPER][3];
-        for (int u = 0; u < BPER; u++)
-            for (int q = 0; q < 3; q++) bold[u][q] = bP[u][q];
+                for (int q = 0; q < 3; q++) (&sJ[q][0][0])[jidx[u]] = jP[S][u][q];
+        // B^{n-1/2} of plane t - 1: with one set in flight copied out so the
+        // next plane can be fetched at once, with two read in place and
+        // refilled after its last use
+        T bold[PF == 1 ? BPER : 1][3];
+        if constexpr (PF == 1)
+            for (int u = 0; u < BPER; u++)
+                for (int q = 0; q < 3; q++) bold[u][q] = bP[S][u][q];
+        auto bget = [&](int u, int q) -> T {
+            if constexpr (PF == 1) return bold[u][q];
+            else return bP[S][u][q];
+        };
         __syncthreads();
-        if (t + 1 <= Z1 + 1) {
-            fetchE(t + 1);
-            if (has_j) fetchJ(t - 1 + P);
+        // the planes of march step t + PF into the set just staged
+        if (t + PF <= Z1 + 1) {
+            fetchE(t + PF, st);
+            if (has_j) fetchJ(t - 2 + P + PF, st);
         }
-        fetchB(t);
+        if constexpr (PF == 1) fetchB(t, st);
         // --- B^{n+1/2} at plane t - 1 on the tile and its one-cell halo
         const int kb = t - 1;
         const int sb = (kb - t0 + 3) % 3;
@@ -195,9 +224,9 @@ __global__ __launch_bounds__(Geo<T>::FT) void k3_front(Coef<T> c, FrontArgs<T> a
                 auto E0 = [&](int q, int dx, int dy) { return sE[sep][q][iy + dy][ix + dx]; };
                 auto E1 = [&](int q) { return sE[se][q][iy][ix]; };   // plane kb + 1
                 const T ex = E0(0, 0, 0), ey = E0(1, 0, 0), ez = E0(2, 0, 0);
-                const T bx = bold[u][0] - (c.tdy * (E0(2, 0, 1) - ez) - c.tdz * (E1(1) - ey));
-                const T by = bold[u][1] - (c.tdz * (E1(0) - ex) - c.tdx * (E0(2, 1, 0) - ez));
-                const T bz = bold[u][2] - (c.tdx * (E0(1, 1, 0) - ey) - c.tdy * (E0(0, 0, 1) - ex));
+                const T bx = bget(u, 0) - (c.tdy * (E0(2, 0, 1) - ez) - c.tdz * (E1(1) - ey));
+                const T by = bget(u, 1) - (c.tdz * (E1(0) - ex) - c.tdx * (E0(2, 1, 0) - ez));
+                const T bz = bget(u, 2) - (c.tdx * (E0(1, 1, 0) - ey) - c.tdy * (E0(0, 0, 1) - ex));
                 sB[sb][0][iy][ix] = bx;
                 sB[sb][1][iy][ix] = by;
                 sB[sb][2][iy][ix] = bz;
@@ -209,6 +238,7 @@ __global__ __launch_bounds__(Geo<T>::FT) void k3_front(Coef<T> c, FrontArgs<T> a
                 }
             }
         }
+        if constexpr (PF == 2) fetchB(t + 1, st);
         // --- x filter of the staged current plane
         if (has_j) {
             for (int u = 0; u < JT::XPER; u++) {
@@ -275,7 +305,14 @@ __global__ __launch_bounds__(Geo<T>::FT) void k3_front(Coef<T> c, FrontArgs<T> a
             a.dEp[2][o] = vz;
             acc += (double)vx * vx + (double)vy * vy + (double)vz * vz;
         }
-    }
+    };
+    int t = t0;
+    if constexpr (PF == 2)
+        for (; t + 1 <= Z1 + 1; t += 2) {
+            body(t, S0{});
+            body(t + 1, S1{});
+        }
+    for (; t <= Z1 + 1; t++) body(t, S0{});
     if (a.partial != nullptr) {
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
         const int lane = tid & 63, w = tid >> 6;

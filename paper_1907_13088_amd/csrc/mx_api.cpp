@@ -391,6 +391,8 @@ int mx_validate(const mx_config *c, int *warn)
     if (ncell_of(c) > (1LL << 40)) return fail(MX_EINVAL, "too many cells");
     if (c->ndim == 2 && (double)ncell_of(c) * (c->dtype == MX_F64 ? 8 : 4) >= 4294967296.0)
         return fail(MX_EINVAL, "2D field arrays must be below 4 GiB (32-bit byte offsets)");
+    if (c->ndim == 3 && (double)c->n[0] * (double)c->n[1] >= 4294967296.0)
+        return fail(MX_EINVAL, "3D planes must hold fewer than 2^32 cells (32-bit in-plane offsets)");
     if (c->dtype != MX_F32 && c->dtype != MX_F64) return fail(MX_EINVAL, "dtype must be MX_F32 or MX_F64");
     if (c->ndim == 2 && (c->blocks < 1 || c->blocks > 3)) return fail(MX_EINVAL, "blocks must be MX_TE, MX_TM or MX_ALL");
     if (c->ndim == 3 && c->blocks != MX_ALL) return fail(MX_EINVAL, "3D grids step all components (MX_ALL)");

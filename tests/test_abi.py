@@ -81,6 +81,8 @@ def _cfg(**kw):
     (dict(ndim=3, n=(8, 8, 8), dt=0.5 / math.sqrt(3), sweeps_per_pass=4), mx.MX_EINVAL),
     (dict(ndim=3, n=(8, 8, 8), dt=0.5 / math.sqrt(3), dtype="f64", sweeps_per_pass=3), mx.MX_EINVAL),
     (dict(ndim=3, n=(8, 8, 8), dt=0.99 / math.sqrt(2)), mx.MX_ECFL),
+    (dict(n=(32768, 32768)), mx.MX_EINVAL),
+    (dict(ndim=3, n=(65536, 65536, 2), dt=0.5 / math.sqrt(3)), mx.MX_EINVAL),
 ])
 def test_validation_errors(kw, code):
     with pytest.raises(mx.MxError) as ei:
