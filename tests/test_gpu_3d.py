@@ -71,6 +71,23 @@ def test_3d_fp32_delta_tolerance_1e7():
     assert max(e) < 1e-5
 
 
+@pytest.mark.parametrize("p,shape", [(0, (21, 22, 23)), (1, (40, 20, 150)), (2, (37, 17, 131)), (1, (6, 9, 5))])
+def test_3d_front_fp32_two_planes_in_flight(p, shape):
+    """The FP32 front keeps two planes in flight (the march unrolled by two)
+    on 128 x 8 tiles: march counts of both parities, several z chunks per
+    column (nz of 37 and 40), tiles wider than the box; within 1e-5 of the
+    FP64 oracle over three steps."""
+    import copy
+    w = I.planewave_3d(n=72 if max(shape) <= 72 else 152, kidx=2, npulses=6, sigma=3.0, filter_passes=p,
+                       tol=0.0, m_max=3, steps=3, seed=3200 + p, dtype="f32")
+    w = _reshape(copy.deepcopy(w), shape)
+    Eg, Bg, _, _ = run_gpu(w, 3, sweeps=3, tol=0.0)
+    Eo, Bo, _ = run_oracle(w, 3, sweeps=3, tol=0.0)
+    e = rel_err(Eg + Bg, Eo + Bo)
+    log(f"3D FP32 front p={p} {shape}: {max(e):.2e}")
+    assert max(e) < 1e-5
+
+
 @pytest.mark.parametrize("dtype,solver,shape", [("f32", 0, (20, 22, 23)), ("f32", 0, (17, 40, 70)),
                                                  ("f32", 0, (5, 3, 7)), ("f64", 0, (20, 22, 23)),
                                                  ("f64", 1, (19, 35, 41)), ("f32", 1, (20, 22, 23))])
