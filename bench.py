@@ -555,6 +555,10 @@ def bench_adjoint(steps, warm):
     every 50 steps (and the same in FP64 beside it)."""
     steps = steps or 500
     cells = 2048 * 2048
+    # an untimed short run of each dtype first: kernel loading and the
+    # library's per-device set-up are not part of a step
+    for dt in ("f32", "f64"):
+        _adjoint_run(2 if warm is None else max(1, warm), dt)
     tf, tb = _adjoint_run(steps, "f32")
     tf64, tb64 = _adjoint_run(steps, "f64")
     return _line("2048^2 adjoint, 256 sources, FP32, 500 steps", cells * steps / (tf + tb) / 1e9, "Gcell-steps/s",

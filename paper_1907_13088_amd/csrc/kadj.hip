@@ -123,24 +123,64 @@ __global__ __launch_bounds__(NT) void k_fill(int64_t n, T *y)
     if (i < n) y[i] = T(0);
 }
 
-// J0 = sum_s amps[s] shape_s, sources applied one after another by a single
-// workgroup so that overlapping windows always add in the same order.
+__device__ __forceinline__ int cyc(int64_t v, int n)
+{
+    const int64_t r = v % n;
+    return (int)(r < 0 ? r + n : r);
+}
+
+// J0 = sum_s amps[s] shape_s (J0 overwritten).  A workgroup owns a BXT x BYT
+// block of cells, one per thread: it lists, in source order, the sources
+// whose (periodically wrapped) windows reach the block and adds them to its
+// cells' sums in that order, so every cell sums its contributions in source
+// order whatever the launch (0 + the first, then each next one).
 template <typename T>
 __global__ __launch_bounds__(NT) void k_src_assemble(int nx, int ny, int nsrc, int W, const int64_t *org,
                                                      const T *shapes, const T *amps, T *Jx, T *Jy, T *Jz)
 {
+    __shared__ int list[NT];
+    __shared__ int wsum[NT / 64];
     T *J[3] = {Jx, Jy, Jz};
-    const int WW = W * W;
-    for (int s = 0; s < nsrc; s++) {
-        const int64_t x0 = org[2 * s], y0 = org[2 * s + 1];
-        const T a = amps[s];
-        for (int t = threadIdx.x; t < WW; t += NT) {
-            const int aa = t / W, bb = t - aa * W;
-            const size_t o = (size_t)(((y0 + aa) % ny + ny) % ny) * nx + (size_t)(((x0 + bb) % nx + nx) % nx);
-            for (int q = 0; q < 3; q++) J[q][o] += a * shapes[((size_t)(s * 3 + q) * W + aa) * W + bb];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int bx0 = blockIdx.x * BXT, by0 = blockIdx.y * BYT;
+    const int bw = min(BXT, nx - bx0), bh = min(BYT, ny - by0);
+    const int i = bx0 + (tid & (BXT - 1)), j = by0 + tid / BXT;
+    const bool own = i < nx && j < ny;
+    T acc[3] = {T(0), T(0), T(0)};
+    for (int c0 = 0; c0 < nsrc; c0 += NT) {
+        // does source c0 + tid reach the block?  (cyclic intervals intersect
+        // when either start lies inside the other interval)
+        const int s = c0 + tid;
+        bool hit = false;
+        if (s < nsrc) {
+            const int xs = cyc(org[2 * s], nx), ys = cyc(org[2 * s + 1], ny);
+            hit = (cyc((int64_t)bx0 - xs, nx) < W || cyc((int64_t)xs - bx0, nx) < bw) &&
+                  (cyc((int64_t)by0 - ys, ny) < W || cyc((int64_t)ys - by0, ny) < bh);
         }
+        // ordered compaction of the hits into list[]
+        const unsigned long long m = __ballot(hit);
+        const int before = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) wsum[wv] = __popcll(m);
         __syncthreads();
+        int base = 0, total = 0;
+        for (int w = 0; w < NT / 64; w++) {
+            if (w < wv) base += wsum[w];
+            total += wsum[w];
+        }
+        if (hit) list[base + before] = s;
+        __syncthreads();
+        if (own)
+            for (int e = 0; e < total; e++) {
+                const int sr = list[e];
+                const int bb = cyc((int64_t)i - org[2 * sr], nx), aa = cyc((int64_t)j - org[2 * sr + 1], ny);
+                if (bb >= W || aa >= W) continue;
+                const T a = amps[sr];
+                for (int q = 0; q < 3; q++) acc[q] += a * shapes[((size_t)(sr * 3 + q) * W + aa) * W + bb];
+            }
+        __syncthreads();   // list[] and wsum[] are reused by the next chunk
     }
+    if (own)
+        for (int q = 0; q < 3; q++) J[q][(size_t)j * nx + i] = acc[q];
 }
 
 // grad[s] = <shape_s, G>, one workgroup per source, fixed-order reduction
@@ -218,10 +258,7 @@ hipError_t launch_sources(int nx, int ny, int nsrc, int W, const int64_t *origin
                           hipStream_t s)
 {
     if (!project) {
-        const int64_t n = (int64_t)nx * ny;
-        const unsigned nb = (unsigned)((n + NT - 1) / NT);
-        for (int q = 0; q < 3; q++) hipLaunchKernelGGL((k_fill<T>), dim3(nb), dim3(NT), 0, s, n, J0[q]);
-        hipLaunchKernelGGL((k_src_assemble<T>), dim3(1), dim3(NT), 0, s, nx, ny, nsrc, W, origins, shapes,
+        hipLaunchKernelGGL((k_src_assemble<T>), grid3(nx, ny, 1), dim3(NT), 0, s, nx, ny, nsrc, W, origins, shapes,
                            amps, J0[0], J0[1], J0[2]);
     } else {
         hipLaunchKernelGGL((k_src_project<T>), dim3(nsrc), dim3(NT), 0, s, nx, ny, W, origins, shapes,
