@@ -45,9 +45,12 @@ __device__ __forceinline__ T avg(T fm, T f0, T fp, int lumped)
 //   x: tdy (vz[j+1] - vz) - tdz (vy[k+1] - vy)
 //   y: tdz (vx[k+1] - vx) - tdx (vz[i+1] - vz)
 //   z: tdx (vy[i+1] - vy) - tdy (vx[j+1] - vx)
+// and, when acc is set, acc += sc v on the stepped components (the current
+// gradient's accumulator, the same axpy as k_axpy, while v is at hand)
 template <typename T>
 __global__ __launch_bounds__(NT) void k_adj_curlB(Coef<T> c, int ndim, int blocks, const T *vx,
-                                                  const T *vy, const T *vz, T *Bx, T *By, T *Bz)
+                                                  const T *vy, const T *vz, T *Bx, T *By, T *Bz, T sc, T *ax,
+                                                  T *ay, T *az)
 {
     Ix id{c.nx, c.ny, c.nz, 0, 0, 0};
     if (!cell(c.nx, c.ny, id)) return;
@@ -74,6 +77,13 @@ __global__ __launch_bounds__(NT) void k_adj_curlB(Coef<T> c, int ndim, int block
         By[o] += avg(ky(0, -1, 0), ky(0, 0, 0), ky(0, 1, 0), L);
     }
     if (te) Bz[o] += d3 ? avg(kz(0, 0, -1), kz(0, 0, 0), kz(0, 0, 1), L) : kz(0, 0, 0);
+    if (ax) {
+        if (te) {
+            ax[o] += sc * vx[o];
+            ay[o] += sc * vy[o];
+        }
+        if (tm) az[o] += sc * vz[o];
+    }
 }
 
 // Ebar -= dt K^T Bbar (the B->E curl of the auxiliary equations, Lambda = 1)
@@ -215,10 +225,11 @@ dim3 grid3(int nx, int ny, int nz) { return dim3((nx + BXT - 1) / BXT, (ny + BYT
 
 template <typename T>
 hipError_t launch_adj_curlB(const Coef<T> &c, int ndim, int blocks, const T *const v[3],
-                            T *const Bbar[3], hipStream_t s)
+                            T *const Bbar[3], T sc, T *const acc[3], hipStream_t s)
 {
     hipLaunchKernelGGL((k_adj_curlB<T>), grid3(c.nx, c.ny, c.nz), dim3(NT), 0, s, c, ndim, blocks,
-                       v[0], v[1], v[2], Bbar[0], Bbar[1], Bbar[2]);
+                       v[0], v[1], v[2], Bbar[0], Bbar[1], Bbar[2], sc, acc ? acc[0] : nullptr,
+                       acc ? acc[1] : nullptr, acc ? acc[2] : nullptr);
     return hipGetLastError();
 }
 
@@ -282,7 +293,7 @@ hipError_t launch_axpy3(int64_t n, int mask, bool zero, T a, const T *const x[3]
 
 #define INST(T)                                                                                       \
     template hipError_t launch_adj_curlB<T>(const Coef<T> &, int, int, const T *const[3], T *const[3], \
-                                            hipStream_t);                                             \
+                                            T, T *const[3], hipStream_t);                             \
     template hipError_t launch_adj_curlE<T>(const Coef<T> &, int, int, const T *const[3], T *const[3], \
                                             hipStream_t);                                             \
     template hipError_t launch_adj_source<T>(const Coef<T> &, int, int, const T *const[3], T *const[3], \

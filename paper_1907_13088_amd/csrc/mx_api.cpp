@@ -1112,16 +1112,17 @@ int adjoint_impl(mx_grid *g, int nsteps, const double *env, const int *sweeps, v
         // v = P Ebar
         int rc = run_sweeps<T>(g, Ebar, target, false, nullptr, e_done, v, nullptr);
         if (rc) return rc;
-        {
-            ProfScope ps(g, MX_PROF_ADJOINT, arr * 9);
-            HIPCHK(launch_adj_curlB<T>(k, c.ndim, c.blocks, v, (T *const *)Bbar, g->stream));
-        }
+        // Bbar += dt Lambda K v, with the current gradient's accumulator
+        // acc += env (-4 pi dt) v in the same pass over v
         const double sc = -(env ? env[s] : 0.0) * c.four_pi * c.dt;
-        if (dJ0 && sc != 0.0) {
-            ProfScope ps(g, MX_PROF_ADJOINT, arr * 3 * 3);
-            HIPCHK(launch_axpy3<T>(g->ncell, cmask, false, (T)sc, v, acc, g->stream));
-            any_src = true;
+        const bool add = dJ0 && sc != 0.0;
+        {
+            const int ncomp = __builtin_popcount(cmask);
+            ProfScope ps(g, MX_PROF_ADJOINT, arr * (9 + (add ? 2 * ncomp : 0)));
+            HIPCHK(launch_adj_curlB<T>(k, c.ndim, c.blocks, v, (T *const *)Bbar, (T)sc, add ? acc : nullptr,
+                                       g->stream));
         }
+        any_src = any_src || add;
         {
             ProfScope ps(g, MX_PROF_ADJOINT, arr * 9);
             HIPCHK(launch_adj_curlE<T>(k, c.ndim, c.blocks, (const T *const *)Bbar, (T *const *)Ebar, g->stream));

@@ -332,9 +332,11 @@ hipError_t launch_tol_init(TolState *st, const double *red, int nblk, hipStream_
 hipError_t launch_tol_decide(TolState *st, const double *red, int b, int k, int buf, double tol, hipStream_t s);
 
 // Adjoint helpers (kadj.hip)
+// Bbar += dt Lambda K v, and acc += sc v on the stepped components when acc
+// is set
 template <typename T>
 hipError_t launch_adj_curlB(const Coef<T> &c, int ndim, int blocks, const T *const v[3],
-                            T *const Bbar[3], hipStream_t s);
+                            T *const Bbar[3], T sc, T *const acc[3], hipStream_t s);
 template <typename T>
 hipError_t launch_adj_curlE(const Coef<T> &c, int ndim, int blocks, const T *const Bbar[3],
                             T *const Ebar[3], hipStream_t s);

@@ -107,6 +107,35 @@ def test_source_windows_assemble_and_project():
     assert np.allclose(grad.cpu().numpy(), ref_grad, rtol=1e-13, atol=1e-13)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_source_assembly_wrapped_overlapping_windows_bitwise(dtype):
+    """J0 = sum_s a_s shape_s with more sources than one chunk of a
+    workgroup's list (600), origins far outside the grid on both sides, a
+    window as wide as the grid's short side and a grid that is not a multiple
+    of the 64 x 4 cell blocks: every cell must equal, bitwise, the sum taken
+    one source after another in source order."""
+    import torch
+    ny, nx, nsrc, W = 37, 150, 600, 37
+    npd = np.float64 if dtype == "f64" else np.float32
+    rng = np.random.default_rng(77)
+    origins = np.stack([rng.integers(-5 * nx, 5 * nx, size=nsrc), rng.integers(-5 * ny, 5 * ny, size=nsrc)], axis=1)
+    shapes = rng.normal(size=(nsrc, 3, W, W)).astype(npd)
+    amps = rng.normal(size=nsrc).astype(npd)
+    want = [np.zeros((ny, nx), dtype=npd) for _ in range(3)]
+    for k in range(nsrc):
+        ys = (origins[k, 1] + np.arange(W)) % ny
+        xs = (origins[k, 0] + np.arange(W)) % nx
+        for c in range(3):
+            want[c][np.ix_(ys, xs)] += amps[k] * shapes[k, c]
+    g = _grid(2, (ny, nx), 0.3, dtype, 0, 0)
+    td = torch.float64 if dtype == "f64" else torch.float32
+    J = [torch.full((ny, nx), float("nan"), dtype=td, device="cuda") for _ in range(3)]
+    g.sources_assemble(torch.tensor(origins, dtype=torch.int64, device="cuda"),
+                       torch.tensor(shapes, device="cuda"), torch.tensor(amps, device="cuda"), J)
+    for a, b in zip(to_np(J), want):
+        assert np.array_equal(a, b)
+
+
 def _probe_loss(E, win):
     return (E[2][win] ** 2).sum()
 
