@@ -18,14 +18,16 @@
 namespace mx {
 namespace small2d {
 
-// Tile shape and threads per workgroup: 1024 threads on a 32 x 8 (FP64) or
-// 32 x 16 (FP32) tile, so that a pass of 8 sweeps (a 48 x 24 or 48 x 32
-// region) has one or two cells per thread and four waves per SIMD hide the
-// LDS round trips of a sweep (128^2 FP64 tolerance solve: 98 against 104 us
-// per step with 256 threads and every pass depth unrolled, 110 with 256
-// threads and the level loop)
+// Tile shape and threads per workgroup: FP64 512 threads on a 32 x 8 tile
+// (a pass of 8 sweeps covers a 48 x 24 region, 2.25 cells per thread), FP32
+// 1024 threads on 32 x 16.  128^2 FP64 tolerance solve, medians of five
+// runs of 1000 steps on one box: 32 x 8 tiles with 512 threads 56.7 us per
+// step, 384 threads 59.1, 768 threads 58.5, 1024 threads 61.3; 32 x 4 tiles
+// 69.2 (512 threads) and 68.6 (1024), 16 x 8 tiles 63.9 and 65.7, 16 x 4
+// tiles 88.5, 32 x 16 tiles of 1024 threads 62.9 (earlier, with every pass
+// depth unrolled: 104 us per step with 256 threads, against 98 with 1024)
 template <typename T> struct Tile;
-template <> struct Tile<double> { static constexpr int TX = 32, TY = 8, NT = 1024; };
+template <> struct Tile<double> { static constexpr int TX = 32, TY = 8, NT = 512; };
 template <> struct Tile<float> { static constexpr int TX = 32, TY = 16, NT = 1024; };
 constexpr int PMAX = 4;   // filter passes
 constexpr int KMAX = 8;   // sweeps per pass
