@@ -26,7 +26,9 @@ namespace batch2d {
 
 constexpr int RX = STRIP;
 
-// largest g with items[g] <= it, items[0] = 0, items[ng] = total
+// largest g with items[g] <= it, items[0] = 0, items[ng] = total.  The
+// result is the same in every lane (it is); read from the first lane it is
+// a scalar, so the grid descriptor's loads are scalar too.
 __device__ __forceinline__ int find_grid(const int *items, int ng, int it)
 {
     int lo = 0, hi = ng;
@@ -34,7 +36,7 @@ __device__ __forceinline__ int find_grid(const int *items, int ng, int it)
         const int mid = (lo + hi) >> 1;
         if (items[mid] <= it) lo = mid; else hi = mid;
     }
-    return lo;
+    return __builtin_amdgcn_readfirstlane(lo);
 }
 
 template <typename T>
@@ -43,6 +45,9 @@ __device__ __forceinline__ void front_item(const GridDesc<T> *d, int ng, const i
 {
     const int g = find_grid(items, ng, it);
     const GridDesc<T> &gd = d[g];
+    // the coefficients as values: through a reference into global memory
+    // the compiler would reload them after every store of a field
+    const Coef<T> c = gd.c;
     FrontArgs<T> fa;
     for (int q = 0; q < 3; q++) {
         fa.E[q] = gd.E[q];
@@ -52,7 +57,7 @@ __device__ __forceinline__ void front_item(const GridDesc<T> *d, int ng, const i
     }
     fa.env_src = T(0);
     fa.partial = nullptr;
-    front2d::front_tile<T, 3, 0, RX, false>(gd.c, fa, gd.B[bin][0], gd.B[bin][1], gd.B[bin][2], L, gd.nsx_f,
+    front2d::front_tile<T, 3, 0, RX, false>(c, fa, gd.B[bin][0], gd.B[bin][1], gd.B[bin][2], L, gd.nsx_f,
                                             it - items[g], 0, lds, sred);
 }
 
@@ -63,6 +68,9 @@ __device__ __forceinline__ void front_sweep_item(const GridDesc<T> *d, int ng, c
 {
     const int g = find_grid(items, ng, it);
     const GridDesc<T> &gd = d[g];
+    // the coefficients as values: through a reference into global memory
+    // the compiler would reload them after every store of a field
+    const Coef<T> c = gd.c;
     FrontArgs<T> fa;
     SweepArgs<T> sa;
     for (int q = 0; q < 3; q++) {
@@ -82,7 +90,7 @@ __device__ __forceinline__ void front_sweep_item(const GridDesc<T> *d, int ng, c
     sa.partial = nullptr;
     sa.skip = nullptr;
     static_assert(fused2d::fs_width<0, K, RX, true>() == STRIP - 32, "fused strips are the front's strips");
-    fused2d::fs_tile<T, 0, K, RX, false, true, 1>(gd.c, fa, gd.B[bin][0], gd.B[bin][1], gd.B[bin][2], sa, L,
+    fused2d::fs_tile<T, 0, K, RX, false, true, 1>(c, fa, gd.B[bin][0], gd.B[bin][1], gd.B[bin][2], sa, L,
                                                   gd.nsx_f, it - items[g], lds);
 }
 
@@ -92,6 +100,9 @@ __device__ __forceinline__ void sweep_item(const GridDesc<T> *d, int ng, const i
 {
     const int g = find_grid(items, ng, it);
     const GridDesc<T> &gd = d[g];
+    // the coefficients as values: through a reference into global memory
+    // the compiler would reload them after every store of a field
+    const Coef<T> c = gd.c;
     SweepArgs<T> sa;
     for (int q = 0; q < 3; q++) {
         sa.rhs[q] = gd.dEp[q];
@@ -103,7 +114,7 @@ __device__ __forceinline__ void sweep_item(const GridDesc<T> *d, int ng, const i
     }
     sa.partial = nullptr;
     sa.skip = nullptr;
-    stream2d::stream_tile<T, 3, K, false, RX, OM>(gd.c, sa, first ? SW_FIRST : 0, L, gd.nsx_s, it - items[g], 0,
+    stream2d::stream_tile<T, 3, K, false, RX, OM>(c, sa, first ? SW_FIRST : 0, L, gd.nsx_s, it - items[g], 0,
                                                   lds, sred);
 }
 

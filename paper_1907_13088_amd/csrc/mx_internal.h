@@ -131,15 +131,21 @@ __device__ __forceinline__ int xcd_map(int b, int n)
 // Element access by a 32-bit byte offset from a uniform base: lets the
 // compiler use the scalar-base + vector-offset addressing form, one offset
 // register shared by every component of a row.  Arrays are below 4 GiB.
+// The access goes through a global-address-space pointer: field arrays are
+// in device global memory, and a base pointer read from memory (a batch's
+// grid descriptor) would otherwise be a generic pointer to the compiler,
+// accessed by flat loads and stores with per-lane 64-bit addresses.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
 template <typename T>
 __device__ __forceinline__ T ld_off(const T *base, unsigned byte_off)
 {
-    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+    return *(gptr<const T>)(reinterpret_cast<const char *>(base) + byte_off);
 }
 template <typename T>
 __device__ __forceinline__ void st_off(T *base, unsigned byte_off, T v)
 {
-    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
+    *(gptr<T>)(reinterpret_cast<char *>(base) + byte_off) = v;
 }
 
 // Store that is not kept in the caches (non-temporal): for results that no
@@ -147,7 +153,7 @@ __device__ __forceinline__ void st_off(T *base, unsigned byte_off, T v)
 template <typename T>
 __device__ __forceinline__ void st_off_nt(T *base, unsigned byte_off, T v)
 {
-    __builtin_nontemporal_store(v, reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off));
+    __builtin_nontemporal_store(v, (gptr<T>)(reinterpret_cast<char *>(base) + byte_off));
 }
 
 // One grid of a batch (device-resident descriptor)
