@@ -405,10 +405,12 @@ hipError_t launch_k(const Coef<T> &c, int flags, const SweepArgs<T> &a, hipStrea
 // (1024 threads; a tile's input rows touch about 3 cache lines for 60 output
 // columns instead of 2 for 28): 512^3, three sweeps per pass, 2.11 against
 // 2.33 ms per delta-form pass and 2.56 against 3.07 per Chebyshev pass; 64 x
-// 8 threads with two rows each measured as 32 x 16.  FP64 and single sweeps:
-// 32 x 16 (a 64 x 16 FP64 tile spills; two rows per thread on a 32 x 8
-// thread block measured the same at three sweeps per pass, 32 x 32 columns
-// slower).
+// 8 threads with two rows each measured as 32 x 16.  FP64 passes of two
+// sweeps: 64 x 16 columns on 64 x 8 threads with two rows each (a 64 x 16
+// FP64 tile of 1024 threads spills), 3.49 against 4.00 ms per delta-form
+// pass at 512^3; the FP64 Chebyshev form spills there and keeps 32 x 16.
+// Single sweeps: 32 x 16 (two rows per thread on a 32 x 8 thread block
+// measured the same at three sweeps per pass, 32 x 32 columns slower).
 template <typename T, int FORM>
 hipError_t launch_form(const Coef<T> &c, int k, int flags, const SweepArgs<T> &a, hipStream_t s, int *nwg)
 {
@@ -417,6 +419,7 @@ hipError_t launch_form(const Coef<T> &c, int k, int flags, const SweepArgs<T> &a
     case 1: return launch_k<T, 1, FORM, 32, 16, 1>(c, flags, a, s, nwg);
     case 2:
         if constexpr (F32) return launch_k<T, 2, FORM, 64, 16, 1>(c, flags, a, s, nwg);
+        else if constexpr (FORM != FM_CHEB) return launch_k<T, 2, FORM, 64, 8, 2>(c, flags, a, s, nwg);
         else return launch_k<T, 2, FORM, 32, 16, 1>(c, flags, a, s, nwg);
     case 3:
         if constexpr (F32) return launch_k<T, 3, FORM, 64, 16, 1>(c, flags, a, s, nwg);
