@@ -46,6 +46,15 @@ constexpr size_t lds_bytes()
     return sw > front_bytes<T>() ? sw : front_bytes<T>();
 }
 
+// Element i of a global array whose pointer is chosen at run time from a
+// small local table (the previous step's increment): read as a global load
+// (through the table the compiler would emit a flat one)
+template <typename T>
+__device__ __forceinline__ T ld_at(const T *p, size_t i)
+{
+    return *(gptr<const T>)(p + i);
+}
+
 // the filter's x weights: binomial(2P, t) / 4^P
 template <int P>
 __device__ __forceinline__ constexpr float binom(int t)
@@ -99,7 +108,7 @@ __device__ __forceinline__ void front(const SmallArgs<T> &a, int s, int bx, int 
         if ((q < 2 && !TE) || (q == 2 && !TM)) continue;
         const size_t o = (size_t)wrapi(Y0 - 1 + iy, ny) * nx + wrapi(X0 - 1 + ix, nx);
         const T *iq = q == 0 ? inc[0] : (q == 1 ? inc[1] : inc[2]);
-        sE[q][iy][ix] = iq ? a.E[q][o] + iq[o] : a.E[q][o];
+        sE[q][iy][ix] = iq ? a.E[q][o] + ld_at(iq, o) : a.E[q][o];
     }
     if (hasj)
         for (int e = tid; e < 3 * JY * JX; e += NT) {
@@ -224,7 +233,7 @@ __device__ __forceinline__ void add_increment(const SmallArgs<T> &a, int bx, int
 #pragma unroll
         for (int q = 0; q < 3; q++) {
             const T *iq = q == 0 ? inc[0] : (q == 1 ? inc[1] : inc[2]);
-            if (iq) a.E[q][o] += iq[o];
+            if (iq) a.E[q][o] += ld_at(iq, o);
         }
     }
 }
