@@ -55,7 +55,8 @@ def _cell_order(sp, d, nx):
 
 
 @pytest.mark.parametrize("d,ordered,npart", [((1.0, 1.0), False, 1500), ((0.9, 1.2), False, 1500),
-                                             ((0.9, 1.2), True, 1500), ((0.9, 1.2), True, 60000)])
+                                             ((0.9, 1.2), True, 1500), ((0.9, 1.2), True, 60000),
+                                             ((0.9, 1.2), True, 150000)])
 def test_push_and_deposit_match_oracle_fp64(d, ordered, npart):
     """One push of two species on a ragged grid: positions, momenta and the
     accumulated current within 1e-12 of the oracle, with the particles in
@@ -63,7 +64,8 @@ def test_push_and_deposit_match_oracle_fp64(d, ordered, npart):
     at 1.4 particles per cell a workgroup's 256 particles span whole rows, so
     they still go to J directly; at 56 per cell they span a few cells and
     their contributions are summed in the LDS tile first (except where they
-    straddle the periodic seam)."""
+    straddle the periodic seam); at 140 per cell most wavefronts share one
+    start cell, so many lanes add to the same LDS nodes at once."""
     import torch
     cfg_o, cfg_g, E, B, species = _setup((29, 37), d, "f64", seed=1, npart=npart)
     if ordered:
