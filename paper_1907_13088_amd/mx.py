@@ -351,10 +351,12 @@ class Grid:
             lib().mx_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter shutdown the HIP runtime may already be gone: leave
-        # the handle to the process exit instead of calling into it
-        if sys.is_finalizing():
+        # the handle to the process exit instead of calling into it (the
+        # check is bound at definition: module globals such as sys may
+        # already be cleared when this runs)
+        if _finalizing():
             return
         try:
             self.close()
@@ -406,10 +408,12 @@ class Batch:
             lib().mx_batch_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter shutdown the HIP runtime may already be gone: leave
-        # the handle to the process exit instead of calling into it
-        if sys.is_finalizing():
+        # the handle to the process exit instead of calling into it (the
+        # check is bound at definition: module globals such as sys may
+        # already be cleared when this runs)
+        if _finalizing():
             return
         try:
             self.close()
