@@ -561,7 +561,7 @@ def bench_adjoint(steps, warm):
         _adjoint_run(2 if warm is None else max(1, warm), dt)
     tf, tb = _adjoint_run(steps, "f32")
     tf64, tb64 = _adjoint_run(steps, "f64")
-    return _line("2048^2 adjoint, 256 sources, FP32, 500 steps", cells * steps / (tf + tb) / 1e9, "Gcell-steps/s",
+    return _line(f"2048^2 adjoint, 256 sources, FP32, {steps} steps", cells * steps / (tf + tb) / 1e9, "Gcell-steps/s",
                  {"steps": steps, "dtype": "f32", "forward_s": round(tf, 3), "backward_s": round(tb, 3),
                   "forward_Gcell_steps_per_s": round(cells * steps / tf / 1e9, 3),
                   "backward_Gcell_steps_per_s": round(cells * steps / tb / 1e9, 3),
